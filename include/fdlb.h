@@ -1,0 +1,161 @@
+/*
+ * fdlb.h -- C ABI of the MI355X (gfx950) finite-difference lattice Boltzmann
+ * (FDLB) solver for the simplified Enskog equation on a 1D wall-bounded
+ * channel (Busuioc & Sofonea, "Bounded flows of dense gases", arXiv 2308.15407).
+ *
+ * What one time step computes (paper references):
+ *   - moments of the weighted populations on the mixed half-range (x) /
+ *     full-range (y, z) Gauss-Hermite lattice (eq:macro_LB, Sec. III.A);
+ *   - the Carnahan-Starling contact value chi (eq:chi), relaxation time
+ *     (eq:viscosity, eq:tau, Kn definition of Sec. II.A) and Prandtl number
+ *     (eq:prandtl);
+ *   - the Shakhov target (eq:j0) plus the first-order Enskog correction J1
+ *     (eq:j1) from 6th-order gradients of ln n, ln chi, ln T, u (Sec. III.B.3),
+ *     projected per axis onto the lattice (eq:hh_gk, eq:H_gk);
+ *   - WENO-5 advection (eq:weno5_flux_x .. eq:weno5_sigma) with diffuse
+ *     walls whose density follows from impenetrability (Sec. III.B), the
+ *     body-force kernel of App. A (eq:kernel_H), advanced by TVD-RK3 (eq:rk3).
+ *
+ * Conventions
+ *   - Reduced units m = k_B = 1; plate separation L = 1; sigma = 1/R with
+ *     R = 1/(6 sqrt2 eta0 chi(eta0) Kn); computational width L_c = 1 - sigma.
+ *   - Velocity index kappa = ((kx*qy) + ky)*qz + kz, kx < qx_half are the
+ *     positive x nodes; populations stored structure-of-arrays f[kappa][cell].
+ *   - All host-side numbers are double.  Every call returns FDLB_OK (0) or a
+ *     negative fdlb_status; fdlb_last_error() returns a thread-local message.
+ *   - Memory: the caller owns one device workspace (size from
+ *     fdlb_workspace_bytes) and the HIP stream; the library never calls
+ *     hipMalloc for them.  The handle owns host-side tables only.
+ *   - Calls are stream-ordered on the caller's stream.  Functions returning
+ *     host data (moments, residuals, state) synchronise that stream.
+ */
+#ifndef FDLB_H
+#define FDLB_H
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum fdlb_status {
+  FDLB_OK = 0,
+  FDLB_EINVAL = -1,     /* invalid parameters or arguments */
+  FDLB_EHIP = -2,       /* a HIP runtime call failed */
+  FDLB_ENOMEM = -3,     /* workspace too small */
+  FDLB_ENONFINITE = -4, /* non-finite or non-positive n or T detected */
+  FDLB_ESTALL = -5,     /* residual stalled or max_steps reached (outputs filled) */
+  FDLB_ESTATE = -6      /* call not valid in the handle's current state */
+};
+
+enum fdlb_flow { FDLB_FOURIER = 0, FDLB_COUETTE = 1, FDLB_POISEUILLE = 2 };
+enum fdlb_collision { FDLB_BGK = 0, FDLB_SHAKHOV_FIXED_PR = 1, FDLB_SHAKHOV_DENSE_PR = 2 };
+enum fdlb_grid { FDLB_GRID_UNIFORM = 0, FDLB_GRID_TANH = 1 };
+enum fdlb_precision { FDLB_F64 = 0, FDLB_F32_BULK = 1 };
+
+/* Problem statement of one channel case (Sec. II.A, Sec. IV, Table tab:quad). */
+typedef struct {
+  int flow;                  /* fdlb_flow; metadata (walls and force define the physics) */
+  double kn;                 /* Knudsen number; <= 0 encodes Kn = infinity (requires eta0 == 0) */
+  double eta0;               /* mean reduced density, [0, 0.5) */
+  double t_left, t_right;    /* wall temperatures */
+  double uy_left, uy_right;  /* wall velocities along y */
+  double ay;                 /* body acceleration along y (Poiseuille) */
+  double n_init, t_init, uy_init; /* uniform initial state (projected Maxwellian) */
+  int nx, grid;              /* cells (>= 7) and fdlb_grid */
+  double stretch;            /* tanh map parameter delta for FDLB_GRID_TANH */
+  int qx_half, qy, qz;       /* half-range order per half (1..32); full-range orders (2..8) */
+  int collision;             /* fdlb_collision */
+  double pr_fixed;           /* Prandtl number for FDLB_SHAKHOV_FIXED_PR */
+  int chi_mode;              /* 0: local Carnahan-Starling chi(eta0 n(x)) */
+  int j1_shear;              /* 1: keep the xi_x xi_y du_y/dx term of J1 (3D operator) */
+  double cfl, dt;            /* dt > 0 overrides dt = cfl * min cell / max |p_x| */
+  int precision;             /* fdlb_precision */
+} fdlb_params;
+
+typedef struct fdlb_ctx *fdlb_handle;
+
+/* Number of moment fields returned per cell: n, u_x, u_y, T, q_x, q_y,
+   P_xx, P_xy, P_yy, P_zz (kinetic parts, eq:macro_LB). */
+#define FDLB_NMOM 10
+
+/* Device workspace bytes for ncases cases (0 when a case is invalid;
+   fdlb_last_error() names it). */
+size_t fdlb_workspace_bytes(const fdlb_params *cases, int ncases);
+
+/* Validate one case and report derived quantities: out[0] = sigma,
+   out[1] = L_c, out[2] = dt, out[3] = K (velocities), out[4] = R. */
+int fdlb_case_info(const fdlb_params *p, double *out5);
+
+/* Host-only helpers (no device needed): the velocity set px, py, pz and
+   lattice weights w ([K] each) and the grid (cell centres x[nx], metric
+   dx/deta jac[nx]) that a case would use. */
+int fdlb_case_lattice(const fdlb_params *p, double *px, double *py, double *pz, double *w);
+int fdlb_case_grid(const fdlb_params *p, double *x, double *jac);
+
+/* Set up ncases independent cases in dev_workspace (bytes long, device
+   memory owned by the caller) on hip_stream (a hipStream_t, may be NULL for
+   the default stream).  Builds the lattice, grid and constant tables on the
+   host, uploads them, and sets every case to its uniform initial state.  The
+   single-case solver is a batch of one. */
+int fdlb_init(const fdlb_params *cases, int ncases, void *dev_workspace, size_t bytes,
+              void *hip_stream, fdlb_handle *out);
+
+/* Advance every active case by nsteps TVD-RK3 steps (asynchronous). */
+int fdlb_step(fdlb_handle h, long nsteps);
+
+/* Moments of case `c` into host_out[FDLB_NMOM][nx] (synchronises). */
+int fdlb_moments(fdlb_handle h, int c, double *host_out);
+
+/* Cell centres x[nx] and metric dx/deta[nx] of case c. */
+int fdlb_grid_coords(fdlb_handle h, int c, double *x, double *jac);
+
+/* Velocity set of case c: px, py, pz and lattice weights w, each [K]. */
+int fdlb_lattice(fdlb_handle h, int c, double *px, double *py, double *pz, double *w);
+
+/* Time step of case c. */
+int fdlb_dt(fdlb_handle h, int c, double *dt);
+
+/* Run all cases until the steady-state residual
+   r = max over n, u_x, u_y, T and cells of |M^{s} - M^{s-1}| / dt
+   drops below tol, checked every check_every steps (converged cases stop
+   advancing).  steps_out[ncases] and resid_out[ncases] receive the step
+   count and last residual.  Returns FDLB_ESTALL if some case did not
+   converge within max_steps (outputs still filled).  In FDLB_F32_BULK mode a
+   case whose residual stalls is promoted to FP64 storage and continues. */
+int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, long check_every,
+                       long *steps_out, double *resid_out);
+
+/* Residual of the last completed step of every case (synchronises):
+   resid_out[ncases]. */
+int fdlb_residual(fdlb_handle h, double *resid_out);
+
+/* Replace the state of case c by the Grad-13-type distribution
+   f = n Proj[f^MB(n,u,T) (1 + Pxy xi_x xi_y/(n T^2) + qx xi_x (xi^2/T - 5)/(5 n T^2))]
+   from host fields[6][nx] = n, u_x, u_y, T, q_x, P_xy, optionally multiplied
+   node by node by (1 + noise[K][nx]) (noise may be NULL). */
+int fdlb_set_state(fdlb_handle h, int c, const double *fields, const double *noise);
+
+/* Copy the populations of case c to / from host memory as double [K][nx]. */
+int fdlb_get_f(fdlb_handle h, int c, double *host_f);
+int fdlb_set_f(fdlb_handle h, int c, const double *host_f);
+
+/* Precision currently used for the bulk of case c (fdlb_precision). */
+int fdlb_case_precision(fdlb_handle h, int c, int *precision);
+
+/* Kernel tuning for all cases: kx values per velocity chunk (0 = automatic)
+   and waves per update block (1, 2, 4 or 8).  Rebuilds the launch maps and
+   drops captured graphs. */
+int fdlb_set_tiling(fdlb_handle h, int kx_per_chunk, int waves_per_block);
+
+/* Capture nsteps steps in a HIP graph that fdlb_step replays (0 disables). */
+int fdlb_set_graph_steps(fdlb_handle h, int nsteps);
+
+/* Release host-side state (the caller still owns the workspace). */
+void fdlb_destroy(fdlb_handle h);
+
+const char *fdlb_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

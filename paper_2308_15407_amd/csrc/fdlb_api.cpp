@@ -1,0 +1,657 @@
+// fdlb_api.cpp -- host driver behind the C ABI of include/fdlb.h.
+//
+// Owns host-side tables only: the caller supplies one device workspace and a
+// stream.  A handle holds a batch of independent cases (a single case is a
+// batch of one); every stage of every active case of one storage precision is
+// one table launch plus one update launch over flat block maps.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "fdlb_common.h"
+#include "fdlb_host.h"
+
+using namespace fdlb;
+
+static thread_local std::string g_err;
+
+static int fail(int code, const std::string &msg) {
+  g_err = msg;
+  return code;
+}
+
+#define HIPCHK(expr)                                                                  \
+  do {                                                                                \
+    hipError_t e_ = (expr);                                                           \
+    if (e_ != hipSuccess) return fail(FDLB_EHIP, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+  } while (0)
+
+struct fdlb_ctx {
+  std::vector<CaseHost> cases;
+  std::vector<CaseDev> hdev;
+  char *ws = nullptr;
+  size_t bytes = 0;
+  hipStream_t stream = nullptr;
+  CaseDev *d_cases = nullptr;
+  unsigned long long *d_resid = nullptr;
+  int *d_map = nullptr;       // map storage (int4 entries)
+  size_t map_cap = 0;         // entries available
+  int *d_mapT[2] = {nullptr, nullptr}, *d_mapU[2] = {nullptr, nullptr};
+  int nT[2] = {0, 0}, nU[2] = {0, 0};
+  int waves = 4;
+  int kx_user = 0;
+  int graph_steps = 0;
+  hipGraphExec_t gexec = nullptr;
+  hipGraph_t graph = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int converge_hist = 20;
+};
+
+static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// per-case workspace arrays
+enum {
+  A_LAT, A_INVDX, A_F64_0, A_F64_1, A_F64_2, A_TX64, A_TYZ64, A_IT64, A_GW64_0, A_GW64_1,
+  A_F32_0, A_F32_1, A_F32_2, A_TX32, A_TYZ32, A_IT32, A_GW32_0, A_GW32_1,
+  A_PART, A_MOM, A_NW, A_FIELDS, A_COUNT
+};
+
+static void case_sizes(const CaseHost &c, size_t *sz) {
+  const size_t nx = c.nx, K = c.K, nkx = 2 * c.qh, qyz = c.qy * c.qz;
+  for (int i = 0; i < A_COUNT; i++) sz[i] = 0;
+  sz[A_LAT] = c.lo.total * 8;
+  sz[A_INVDX] = nx * 8;
+  sz[A_F64_0] = sz[A_F64_1] = sz[A_F64_2] = K * nx * 8;
+  sz[A_TX64] = 4 * nkx * nx * 8;
+  sz[A_TYZ64] = 4 * qyz * nx * 8;
+  sz[A_IT64] = nx * 8;
+  sz[A_GW64_0] = sz[A_GW64_1] = K * 8;
+  if (c.p.precision == FDLB_F32_BULK) {
+    sz[A_F32_0] = sz[A_F32_1] = sz[A_F32_2] = K * nx * 4;
+    sz[A_TX32] = 4 * nkx * nx * 4;
+    sz[A_TYZ32] = 4 * qyz * nx * 4;
+    sz[A_IT32] = nx * 4;
+    sz[A_GW32_0] = sz[A_GW32_1] = K * 4;
+  }
+  sz[A_PART] = nkx * NRAW * nx * 8;  // enough for one chunk per kx
+  sz[A_MOM] = FDLB_NMOM * nx * 8;
+  sz[A_NW] = 2 * 8;
+  sz[A_FIELDS] = 6 * nx * 8;
+}
+
+static size_t map_entries(const std::vector<CaseHost> &cs) {
+  size_t n = 0;
+  for (auto &c : cs) {
+    const int nkx = 2 * c.qh;
+    n += (size_t)((c.nx + CTILE - 1) / CTILE + 2) + (size_t)((c.nx + UTILE - 1) / UTILE) * nkx;
+  }
+  return 2 * n;  // room for both precision groups
+}
+
+static size_t header_bytes(int ncases, size_t mapn) {
+  return align256(sizeof(CaseDev) * ncases) + align256(8 * (size_t)ncases) + align256(16 * mapn);
+}
+
+static size_t total_bytes(const std::vector<CaseHost> &cs) {
+  size_t b = header_bytes((int)cs.size(), map_entries(cs));
+  size_t sz[A_COUNT];
+  for (auto &c : cs) {
+    case_sizes(c, sz);
+    for (int i = 0; i < A_COUNT; i++) b += align256(sz[i]);
+  }
+  return b;
+}
+
+static int build_all(const fdlb_params *ps, int n, std::vector<CaseHost> &cs) {
+  if (!ps || n <= 0) return fail(FDLB_EINVAL, "need at least one case");
+  cs.resize(n);
+  for (int i = 0; i < n; i++) {
+    std::string why;
+    if (build_case(ps[i], cs[i], why)) return fail(FDLB_EINVAL, "case " + std::to_string(i) + ": " + why);
+  }
+  return FDLB_OK;
+}
+
+extern "C" const char *fdlb_last_error(void) { return g_err.c_str(); }
+
+extern "C" size_t fdlb_workspace_bytes(const fdlb_params *cases, int ncases) {
+  std::vector<CaseHost> cs;
+  if (build_all(cases, ncases, cs)) return 0;
+  return total_bytes(cs);
+}
+
+extern "C" int fdlb_case_info(const fdlb_params *p, double *out5) {
+  if (!p || !out5) return fail(FDLB_EINVAL, "null argument");
+  CaseHost c;
+  std::string why;
+  if (build_case(*p, c, why)) return fail(FDLB_EINVAL, why);
+  out5[0] = c.sigma; out5[1] = c.Lc; out5[2] = c.dt; out5[3] = c.K; out5[4] = c.R;
+  return FDLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// launch maps
+// ---------------------------------------------------------------------------
+static int auto_kxc(const CaseHost &c, int waves) {
+  // aim for a chunk of about waves*4 y-lines per block, at least one kx
+  const int lines_per_kx = c.qz;
+  int kxc = std::max(1, (waves * 4) / std::max(1, lines_per_kx));
+  return std::min(kxc, 2 * c.qh);
+}
+
+static int upload_cases(fdlb_ctx *h) {
+  HIPCHK(hipMemcpyAsync(h->d_cases, h->hdev.data(), sizeof(CaseDev) * h->hdev.size(), hipMemcpyHostToDevice,
+                        h->stream));
+  return FDLB_OK;
+}
+
+static void drop_graph(fdlb_ctx *h) {
+  if (h->gexec) { (void)hipGraphExecDestroy(h->gexec); h->gexec = nullptr; }
+  if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
+}
+
+static int build_maps(fdlb_ctx *h) {
+  drop_graph(h);
+  std::vector<int> mt[2], mu[2];
+  for (size_t ci = 0; ci < h->cases.size(); ci++) {
+    CaseHost &c = h->cases[ci];
+    CaseDev &d = h->hdev[ci];
+    c.kxc = h->kx_user > 0 ? std::min(h->kx_user, 2 * c.qh) : auto_kxc(c, h->waves);
+    c.nchunk = (2 * c.qh + c.kxc - 1) / c.kxc;
+    d.kxc = c.kxc; d.nchunk = c.nchunk;
+    d.active = c.active ? 1 : 0;
+    d.prec = c.prec;
+    if (!c.active) continue;
+    const int P = c.prec;
+    const int nct = (c.nx + CTILE - 1) / CTILE, nut = (c.nx + UTILE - 1) / UTILE;
+    for (int t = 0; t < nct; t++) { mt[P].insert(mt[P].end(), {(int)ci, t, 0, 0}); }
+    mt[P].insert(mt[P].end(), {(int)ci, -1, 0, 0});
+    mt[P].insert(mt[P].end(), {(int)ci, -2, 0, 0});
+    for (int ch = 0; ch < c.nchunk; ch++)
+      for (int t = 0; t < nut; t++) mu[P].insert(mu[P].end(), {(int)ci, t, ch, 0});
+  }
+  size_t need = 0;
+  for (int P = 0; P < 2; P++) need += (mt[P].size() + mu[P].size()) / 4;
+  if (need > h->map_cap) return fail(FDLB_ENOMEM, "launch map exceeds its reserved space");
+  size_t off = 0;
+  for (int P = 0; P < 2; P++) {
+    h->d_mapT[P] = h->d_map + 4 * off;
+    h->nT[P] = (int)(mt[P].size() / 4);
+    if (!mt[P].empty())
+      HIPCHK(hipMemcpyAsync(h->d_mapT[P], mt[P].data(), mt[P].size() * 4, hipMemcpyHostToDevice, h->stream));
+    off += mt[P].size() / 4;
+    h->d_mapU[P] = h->d_map + 4 * off;
+    h->nU[P] = (int)(mu[P].size() / 4);
+    if (!mu[P].empty())
+      HIPCHK(hipMemcpyAsync(h->d_mapU[P], mu[P].data(), mu[P].size() * 4, hipMemcpyHostToDevice, h->stream));
+    off += mu[P].size() / 4;
+  }
+  int r = upload_cases(h);
+  if (r) return r;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FDLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// stage launches
+// ---------------------------------------------------------------------------
+static int launch_steps(fdlb_ctx *h, long nsteps, hipStream_t s) {
+  for (long k = 0; k < nsteps; k++)
+    for (int stage = 1; stage <= 3; stage++)
+      for (int P = 0; P < 2; P++) {
+        if (h->nU[P] == 0) continue;
+        int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
+        HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], mode, stage - 1, s));
+        HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[P], h->nU[P], h->waves, s));
+      }
+  return FDLB_OK;
+}
+
+static int launch_moments(fdlb_ctx *h, bool resid) {
+  if (resid) HIPCHK(launch_zero_resid(h->d_cases, (int)h->cases.size(), h->stream));
+  for (int P = 0; P < 2; P++)
+    HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P],
+                        TM_PARTIALS | TM_WRITE_MOM | (resid ? TM_RESID : 0), 0, h->stream));
+  return FDLB_OK;
+}
+
+static int capture_graph(fdlb_ctx *h) {
+  drop_graph(h);
+  if (!h->cap_stream) HIPCHK(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking));
+  HIPCHK(hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal));
+  int r = launch_steps(h, h->graph_steps, h->cap_stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(h->cap_stream, &g);
+  if (r) { if (g) (void)hipGraphDestroy(g); return r; }
+  if (e != hipSuccess) return fail(FDLB_EHIP, std::string("graph capture: ") + hipGetErrorString(e));
+  h->graph = g;
+  HIPCHK(hipGraphInstantiate(&h->gexec, g, nullptr, nullptr, 0));
+  return FDLB_OK;
+}
+
+static int do_steps(fdlb_ctx *h, long nsteps) {
+  long left = nsteps;
+  if (h->graph_steps > 0 && nsteps >= h->graph_steps) {
+    if (!h->gexec) { int r = capture_graph(h); if (r) return r; }
+    while (left >= h->graph_steps) {
+      HIPCHK(hipGraphLaunch(h->gexec, h->stream));
+      left -= h->graph_steps;
+    }
+  }
+  if (left > 0) { int r = launch_steps(h, left, h->stream); if (r) return r; }
+  for (auto &c : h->cases)
+    if (c.active) c.steps += nsteps;
+  return FDLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// init
+// ---------------------------------------------------------------------------
+static int set_state_dev(fdlb_ctx *h, int ci, const double *fields, const double *noise) {
+  CaseHost &c = h->cases[ci];
+  CaseDev &d = h->hdev[ci];
+  HIPCHK(hipMemcpyAsync(d.fields, fields, sizeof(double) * 6 * c.nx, hipMemcpyHostToDevice, h->stream));
+  if (noise) HIPCHK(hipMemcpyAsync(d.noise, noise, sizeof(double) * c.K * c.nx, hipMemcpyHostToDevice, h->stream));
+  // a one-case map for this case only
+  const int P = c.prec;
+  std::vector<int> mt, mu;
+  const int nct = (c.nx + CTILE - 1) / CTILE, nut = (c.nx + UTILE - 1) / UTILE;
+  for (int t = 0; t < nct; t++) mt.insert(mt.end(), {ci, t, 0, 0});
+  for (int ch = 0; ch < c.nchunk; ch++)
+    for (int t = 0; t < nut; t++) mu.insert(mu.end(), {ci, t, ch, 0});
+  // stage the map at the end of the map area (never used by the stepping maps)
+  int *tmp = h->d_map + 4 * (h->map_cap - (mt.size() + mu.size()) / 4);
+  HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, h->stream));
+  HIPCHK(launch_fill(P, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, noise ? 1 : 0, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  c.steps = 0;
+  c.last_resid = INFINITY;
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_init(const fdlb_params *ps, int ncases, void *dev_ws, size_t bytes, void *stream,
+                         fdlb_handle *out) {
+  if (!out) return fail(FDLB_EINVAL, "null handle pointer");
+  *out = nullptr;
+  fdlb_ctx *h = new fdlb_ctx();
+  int r = build_all(ps, ncases, h->cases);
+  if (r) { delete h; return r; }
+  size_t need = total_bytes(h->cases);
+  if (!dev_ws || bytes < need) {
+    delete h;
+    return fail(FDLB_ENOMEM, "workspace too small: need " + std::to_string(need) + " bytes");
+  }
+  h->ws = (char *)dev_ws;
+  h->bytes = bytes;
+  h->stream = (hipStream_t)stream;
+  const int nc = ncases;
+  h->map_cap = map_entries(h->cases);
+  char *p = h->ws;
+  h->d_cases = (CaseDev *)p; p += align256(sizeof(CaseDev) * nc);
+  h->d_resid = (unsigned long long *)p; p += align256(8 * (size_t)nc);
+  h->d_map = (int *)p; p += align256(16 * h->map_cap);
+  h->hdev.assign(nc, CaseDev());
+  for (int i = 0; i < nc; i++) {
+    CaseHost &c = h->cases[i];
+    CaseDev &d = h->hdev[i];
+    memset(&d, 0, sizeof(d));
+    size_t sz[A_COUNT];
+    case_sizes(c, sz);
+    char *arr[A_COUNT];
+    for (int a = 0; a < A_COUNT; a++) {
+      arr[a] = sz[a] ? p : nullptr;
+      c.ws_off[a] = (size_t)(p - h->ws);
+      p += align256(sz[a]);
+    }
+    c.prec = c.p.precision;
+    c.active = true;
+    d.nx = c.nx; d.qh = c.qh; d.qy = c.qy; d.qz = c.qz; d.K = c.K; d.nkx = 2 * c.qh; d.qyz = c.qy * c.qz;
+    d.ntile_u = (c.nx + UTILE - 1) / UTILE; d.ntile_c = (c.nx + CTILE - 1) / CTILE;
+    d.collision = c.p.collision; d.j1_shear = c.p.j1_shear;
+    d.eta0 = c.p.eta0; d.kn = c.p.kn; d.chi0 = c.chi0; d.pr_fixed = c.p.pr_fixed; d.ay = c.p.ay; d.dt = c.dt;
+    d.tau_pre = c.p.kn > 0 ? 5.0 * sqrt(2.0 * M_PI) / 16.0 * c.p.kn * c.chi0 : 0.0;
+    d.wallD[0] = c.wallD[0]; d.wallD[1] = c.wallD[1];
+    d.lat = (double *)arr[A_LAT];
+    d.lo = c.lo;
+    d.invdx = (double *)arr[A_INVDX];
+    d.f[0][0] = arr[A_F64_0]; d.f[0][1] = arr[A_F64_1]; d.f[0][2] = arr[A_F64_2];
+    d.tabX[0] = arr[A_TX64]; d.tabYZ[0] = arr[A_TYZ64]; d.invtau[0] = arr[A_IT64];
+    d.gw[0][0] = arr[A_GW64_0]; d.gw[0][1] = arr[A_GW64_1];
+    d.f[1][0] = arr[A_F32_0]; d.f[1][1] = arr[A_F32_1]; d.f[1][2] = arr[A_F32_2];
+    d.tabX[1] = arr[A_TX32]; d.tabYZ[1] = arr[A_TYZ32]; d.invtau[1] = arr[A_IT32];
+    d.gw[1][0] = arr[A_GW32_0]; d.gw[1][1] = arr[A_GW32_1];
+    d.part = (double *)arr[A_PART];
+    d.mom = (double *)arr[A_MOM];
+    d.nw = (double *)arr[A_NW];
+    d.resid = h->d_resid + i;
+    d.fields = (double *)arr[A_FIELDS];
+    d.noise = (double *)arr[A_F64_1];   // f^(1) is free while a state is being set
+    HIPCHK(hipMemcpyAsync(d.lat, c.lat.data(), sizeof(double) * c.lo.total, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(d.invdx, c.invdx.data(), sizeof(double) * c.nx, hipMemcpyHostToDevice, h->stream));
+    for (int w = 0; w < 2; w++) {
+      HIPCHK(hipMemcpyAsync(d.gw[0][w], c.gw[w].data(), sizeof(double) * c.K, hipMemcpyHostToDevice, h->stream));
+      if (d.gw[1][w]) {
+        std::vector<float> g32(c.gw[w].begin(), c.gw[w].end());
+        HIPCHK(hipMemcpyAsync(d.gw[1][w], g32.data(), sizeof(float) * c.K, hipMemcpyHostToDevice, h->stream));
+        HIPCHK(hipStreamSynchronize(h->stream));
+      }
+    }
+  }
+  if ((size_t)(p - h->ws) > bytes) { delete h; return fail(FDLB_ENOMEM, "workspace layout overflow"); }
+  r = build_maps(h);
+  if (r) { delete h; return r; }
+  for (int i = 0; i < nc; i++) {
+    CaseHost &c = h->cases[i];
+    std::vector<double> fl(6 * (size_t)c.nx, 0.0);
+    for (int k = 0; k < c.nx; k++) { fl[k] = c.p.n_init; fl[2 * c.nx + k] = c.p.uy_init; fl[3 * c.nx + k] = c.p.t_init; }
+    r = set_state_dev(h, i, fl.data(), nullptr);
+    if (r) { delete h; return r; }
+  }
+  *out = h;
+  return FDLB_OK;
+}
+
+extern "C" void fdlb_destroy(fdlb_handle h) {
+  if (!h) return;
+  drop_graph(h);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  delete h;
+}
+
+static int check_case(fdlb_ctx *h, int c) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  if (c < 0 || c >= (int)h->cases.size()) return fail(FDLB_EINVAL, "case index out of range");
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_step(fdlb_handle h, long nsteps) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  if (nsteps < 0) return fail(FDLB_EINVAL, "negative step count");
+  return do_steps(h, nsteps);
+}
+
+extern "C" int fdlb_moments(fdlb_handle h, int c, double *out) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (!out) return fail(FDLB_EINVAL, "null output");
+  bool was = h->cases[c].active;
+  if (!was) {   // a retired case keeps its last moments; refresh them anyway
+    h->hdev[c].active = 1;
+    r = upload_cases(h); if (r) return r;
+  }
+  std::vector<int> mt;
+  const CaseHost &ch = h->cases[c];
+  for (int t = 0; t < (ch.nx + CTILE - 1) / CTILE; t++) mt.insert(mt.end(), {c, t, 0, 0});
+  int *tmp = h->d_map + 4 * (h->map_cap - mt.size() / 4);
+  HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, (int)(mt.size() / 4), TM_PARTIALS | TM_WRITE_MOM, 0, h->stream));
+  HIPCHK(hipMemcpyAsync(out, h->hdev[c].mom, sizeof(double) * FDLB_NMOM * ch.nx, hipMemcpyDeviceToHost, h->stream));
+  if (!was) { h->hdev[c].active = 0; r = upload_cases(h); if (r) return r; }
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_grid_coords(fdlb_handle h, int c, double *x, double *jac) {
+  int r = check_case(h, c);
+  if (r) return r;
+  const CaseHost &ch = h->cases[c];
+  if (x) memcpy(x, ch.x.data(), sizeof(double) * ch.nx);
+  if (jac) memcpy(jac, ch.jac.data(), sizeof(double) * ch.nx);
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_lattice(fdlb_handle h, int c, double *px, double *py, double *pz, double *w) {
+  int r = check_case(h, c);
+  if (r) return r;
+  const CaseHost &ch = h->cases[c];
+  for (int kx = 0; kx < 2 * ch.qh; kx++)
+    for (int ky = 0; ky < ch.qy; ky++)
+      for (int kz = 0; kz < ch.qz; kz++) {
+        int k = (kx * ch.qy + ky) * ch.qz + kz;
+        if (px) px[k] = ch.lat[ch.lo.px + kx];
+        if (py) py[k] = ch.lat[ch.lo.py + ky];
+        if (pz) pz[k] = ch.lat[ch.lo.pz + kz];
+        if (w) w[k] = ch.wx[kx] * ch.wy[ky] * ch.wz[kz];
+      }
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_dt(fdlb_handle h, int c, double *dt) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (dt) *dt = h->cases[c].dt;
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_case_precision(fdlb_handle h, int c, int *prec) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (prec) *prec = h->cases[c].prec;
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_set_state(fdlb_handle h, int c, const double *fields, const double *noise) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (!fields) return fail(FDLB_EINVAL, "null fields");
+  const CaseHost &ch = h->cases[c];
+  for (int i = 0; i < ch.nx; i++)
+    if (!(fields[i] > 0) || !(fields[3 * ch.nx + i] > 0)) return fail(FDLB_EINVAL, "fields need n > 0 and T > 0");
+  bool was = h->hdev[c].active;
+  h->hdev[c].active = 1;
+  r = upload_cases(h); if (r) return r;
+  r = set_state_dev(h, c, fields, noise);
+  if (r) return r;
+  if (!was) { h->hdev[c].active = 0; r = upload_cases(h); if (r) return r; }
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_get_f(fdlb_handle h, int c, double *host_f) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (!host_f) return fail(FDLB_EINVAL, "null output");
+  const CaseHost &ch = h->cases[c];
+  const size_t n = (size_t)ch.K * ch.nx;
+  if (ch.prec == 0) {
+    HIPCHK(hipMemcpyAsync(host_f, h->hdev[c].f[0][0], n * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } else {
+    std::vector<float> tmp(n);
+    HIPCHK(hipMemcpyAsync(tmp.data(), h->hdev[c].f[1][0], n * 4, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (size_t i = 0; i < n; i++) host_f[i] = tmp[i];
+  }
+  return FDLB_OK;
+}
+
+static int refresh_partials(fdlb_ctx *h, int c) {
+  const CaseHost &ch = h->cases[c];
+  std::vector<int> mt, mu;
+  const int nct = (ch.nx + CTILE - 1) / CTILE, nut = (ch.nx + UTILE - 1) / UTILE;
+  for (int t = 0; t < nct; t++) mt.insert(mt.end(), {c, t, 0, 0});
+  for (int ch_ = 0; ch_ < ch.nchunk; ch_++)
+    for (int t = 0; t < nut; t++) mu.insert(mu.end(), {c, t, ch_, 0});
+  int *tmp = h->d_map + 4 * (h->map_cap - (mt.size() + mu.size()) / 4);
+  HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
+  HIPCHK(launch_partials(ch.prec, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, h->stream));
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_set_f(fdlb_handle h, int c, const double *host_f) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (!host_f) return fail(FDLB_EINVAL, "null input");
+  const CaseHost &ch = h->cases[c];
+  const size_t n = (size_t)ch.K * ch.nx;
+  if (ch.prec == 0) {
+    HIPCHK(hipMemcpyAsync(h->hdev[c].f[0][0], host_f, n * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  } else {
+    std::vector<float> tmp(host_f, host_f + n);
+    HIPCHK(hipMemcpyAsync(h->hdev[c].f[1][0], tmp.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+  }
+  bool was = h->hdev[c].active;
+  h->hdev[c].active = 1;
+  r = upload_cases(h); if (r) return r;
+  r = refresh_partials(h, c);
+  if (r) return r;
+  if (!was) { h->hdev[c].active = 0; r = upload_cases(h); if (r) return r; }
+  h->cases[c].steps = 0;
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_set_tiling(fdlb_handle h, int kx_per_chunk, int waves) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  if (!(waves == 1 || waves == 2 || waves == 4 || waves == 8)) return fail(FDLB_EINVAL, "waves must be 1, 2, 4 or 8");
+  if (kx_per_chunk < 0) return fail(FDLB_EINVAL, "negative kx_per_chunk");
+  HIPCHK(hipStreamSynchronize(h->stream));
+  h->waves = waves;
+  h->kx_user = kx_per_chunk;
+  int r = build_maps(h);
+  if (r) return r;
+  // the partial sums must follow the new chunking
+  for (size_t c = 0; c < h->cases.size(); c++)
+    if (h->cases[c].active) { r = refresh_partials(h, (int)c); if (r) return r; }
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_set_graph_steps(fdlb_handle h, int nsteps) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  if (nsteps < 0) return fail(FDLB_EINVAL, "negative graph length");
+  drop_graph(h);
+  h->graph_steps = nsteps;
+  return FDLB_OK;
+}
+
+static int read_resid(fdlb_ctx *h, std::vector<double> &r) {
+  const int nc = (int)h->cases.size();
+  std::vector<unsigned long long> bits(nc);
+  int e = launch_moments(h, true);
+  if (e) return e;
+  HIPCHK(hipMemcpyAsync(bits.data(), h->d_resid, 8 * (size_t)nc, hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  r.resize(nc);
+  for (int i = 0; i < nc; i++) {
+    double v;
+    memcpy(&v, &bits[i], 8);
+    r[i] = h->cases[i].active ? v : h->cases[i].last_resid;
+  }
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_residual(fdlb_handle h, double *out) {
+  if (!h || !out) return fail(FDLB_EINVAL, "null argument");
+  std::vector<double> r;
+  int e = read_resid(h, r);
+  if (e) return e;
+  for (size_t i = 0; i < r.size(); i++) out[i] = r[i];
+  return FDLB_OK;
+}
+
+static int promote_case(fdlb_ctx *h, int c) {
+  CaseHost &ch = h->cases[c];
+  CaseDev &d = h->hdev[c];
+  const size_t n = (size_t)ch.K * ch.nx;
+  HIPCHK(launch_convert(0, d.f[1][0], d.f[0][0], n, h->stream));
+  ch.prec = 0;
+  d.prec = 0;
+  int r = upload_cases(h);
+  if (r) return r;
+  r = build_maps(h);
+  if (r) return r;
+  return refresh_partials(h, c);
+}
+
+extern "C" int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, long check_every, long *steps_out,
+                                  double *resid_out) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  if (!(tol > 0) || max_steps < 0 || check_every <= 0) return fail(FDLB_EINVAL, "bad tol / max_steps / check_every");
+  const int nc = (int)h->cases.size();
+  std::vector<long> start(nc);
+  std::vector<double> best(nc, INFINITY);
+  std::vector<int> since_best(nc, 0);
+  for (int i = 0; i < nc; i++) { start[i] = h->cases[i].steps; h->cases[i].active = true; }
+  int r = build_maps(h);
+  if (r) return r;
+  bool nonfinite = false;
+  std::vector<double> res;
+  for (;;) {
+    // cases still running and the largest number of steps any may still take
+    long room = 0;
+    int running = 0;
+    for (int i = 0; i < nc; i++)
+      if (h->cases[i].active) { running++; room = std::max(room, max_steps - (h->cases[i].steps - start[i])); }
+    if (running == 0 || room <= 0) break;
+    long chunk = std::min(check_every, room);
+    r = do_steps(h, chunk);
+    if (r) return r;
+    r = read_resid(h, res);
+    if (r) return r;
+    bool changed = false;
+    for (int i = 0; i < nc; i++) {
+      CaseHost &c = h->cases[i];
+      if (!c.active) continue;
+      c.last_resid = res[i];
+      if (!(res[i] == res[i]) || std::isinf(res[i])) { c.active = false; changed = true; nonfinite = true; continue; }
+      if (res[i] < tol || c.steps - start[i] >= max_steps) { c.active = false; changed = true; continue; }
+      if (res[i] < 0.9 * best[i]) { best[i] = res[i]; since_best[i] = 0; }
+      else if (++since_best[i] >= h->converge_hist && c.prec == 1) {
+        r = promote_case(h, i);
+        if (r) return r;
+        best[i] = INFINITY; since_best[i] = 0;
+      }
+    }
+    if (changed) { r = build_maps(h); if (r) return r; }
+  }
+  bool all = true;
+  for (int i = 0; i < nc; i++) {
+    if (steps_out) steps_out[i] = h->cases[i].steps - start[i];
+    if (resid_out) resid_out[i] = h->cases[i].last_resid;
+    if (!(h->cases[i].last_resid < tol)) all = false;
+    h->cases[i].active = true;
+  }
+  r = build_maps(h);
+  if (r) return r;
+  if (nonfinite) return fail(FDLB_ENONFINITE, "non-finite or non-positive moments");
+  if (!all) return fail(FDLB_ESTALL, "residual did not reach tol within max_steps");
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_case_lattice(const fdlb_params *p, double *px, double *py, double *pz, double *w) {
+  if (!p) return fail(FDLB_EINVAL, "null params");
+  CaseHost ch;
+  std::string why;
+  if (build_case(*p, ch, why)) return fail(FDLB_EINVAL, why);
+  for (int kx = 0; kx < 2 * ch.qh; kx++)
+    for (int ky = 0; ky < ch.qy; ky++)
+      for (int kz = 0; kz < ch.qz; kz++) {
+        int k = (kx * ch.qy + ky) * ch.qz + kz;
+        if (px) px[k] = ch.lat[ch.lo.px + kx];
+        if (py) py[k] = ch.lat[ch.lo.py + ky];
+        if (pz) pz[k] = ch.lat[ch.lo.pz + kz];
+        if (w) w[k] = ch.wx[kx] * ch.wy[ky] * ch.wz[kz];
+      }
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_case_grid(const fdlb_params *p, double *x, double *jac) {
+  if (!p) return fail(FDLB_EINVAL, "null params");
+  CaseHost ch;
+  std::string why;
+  if (build_case(*p, ch, why)) return fail(FDLB_EINVAL, why);
+  if (x) memcpy(x, ch.x.data(), sizeof(double) * ch.nx);
+  if (jac) memcpy(jac, ch.jac.data(), sizeof(double) * ch.nx);
+  return FDLB_OK;
+}

@@ -1,0 +1,121 @@
+// fdlb_common.h -- data layout shared by the host driver and the gfx950
+// kernels of the FDLB channel solver, plus the per-axis projection formulas
+// used both on the host (wall tables) and on the device (per-cell tables).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdlb {
+
+constexpr int NB = 48;         // nodes of the half-range base rule used for projections
+constexpr int MAXQH = 32;      // largest half-range order per half
+constexpr int MAXQY = 8;       // largest full-range order on y and z
+constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
+constexpr int CTILE = 32;      // cells per table block
+constexpr int CHALO = 6;       // moment halo of a table block
+constexpr int NRAW = 9;        // raw moment sums per cell
+
+// Offsets (in doubles) of the lattice constants of one case.
+struct LatOff {
+  int px, py, pz;   // node coordinates: [2qh], [qy], [qz]
+  int kmat;         // momentum-derivative kernel [qy*qy] (App. A)
+  int bP, bA;       // base rule nodes P_m and A_m = ln W_m + P_m^2/2, [NB] each
+  int lam;          // Lagrange basis of the lattice nodes at the base nodes [qh*NB]
+  int hQ;           // h_Q at the base nodes [NB]
+  int ck;           // 1/h_Q'(p_k) [qh]
+  int Hy, Hz;       // w_k He_l(p_k)/l!  [qy*qy], [qz*qz]
+  int fdw;          // one-sided 7-point first-derivative weights, rows for cells 0,1,2 [3*7]
+  int total;
+};
+
+// One case as the kernels see it (lives in device memory).
+struct CaseDev {
+  int nx, qh, qy, qz, K, nkx, qyz;
+  int nchunk, kxc, ntile_u, ntile_c;
+  int prec;             // active storage: 0 double, 1 float
+  int collision, j1_shear;
+  int active;
+  int pad0;
+  double eta0, kn, chi0, pr_fixed, ay, dt;
+  double tau_pre;       // (5 sqrt(2 pi)/16) Kn chi0 ; 0 when Kn = infinity
+  double wallD[2];      // sum over emitted nodes of p_x g^w (left, right)
+  double *lat;          // lattice constants
+  LatOff lo;
+  double *invdx;        // [nx] 1/(J_i deta)
+  void *f[2][3];        // populations f^n, f^(1), f^(2) per storage precision
+  void *tabX[2];        // n X_a[kx] at [a][kx][cell]
+  void *tabYZ[2];       // YZ_a[ky*qz+kz] at [a][yz][cell]
+  void *invtau[2];      // [nx]
+  void *gw[2][2];       // projected wall Maxwellians (n = 1) [K], per precision, per wall
+  double *part;         // partial raw sums [nchunk][NRAW][nx]
+  double *mom;          // [10][nx] moments of f^n (as of the last stage-1 table pass)
+  double *nw;           // [2] wall densities of the current stage input
+  unsigned long long *resid;  // residual bits (max of non-negative doubles)
+  double *fields;       // staging [6][nx] for set_state
+  double *noise;        // staging [K][nx] for set_state (may be unused)
+};
+
+// ---------------------------------------------------------------------------
+// projection formulas
+// ---------------------------------------------------------------------------
+
+// Half-range table of g(p) (p-u)^a, a = 0..3, at the positive nodes p_k for the
+// positive half line.  With the base-rule weights G_m = W_m g(P_m)/omega(P_m)
+// the Lagrange identity gives X_0[k] = sum_m G_m l_k(P_m); higher powers use
+// (p-u)^a l_k(p) = (p_k-u)^a l_k(p) + h_Q(p)/h_Q'(p_k) sum_{b<a} (p_k-u)^{a-1-b} (p-u)^b.
+// The negative half follows from X^-_a(u) = (-1)^a X^+_a(-u).
+__host__ __device__ inline double base_weight(const double *lat, const LatOff &lo, int m, double u,
+                                              double T, double rsT) {
+  double d = lat[lo.bP + m] - u;
+  return exp(lat[lo.bA + m] - d * d / (2.0 * T)) * rsT;
+}
+
+// full-range Hermite coefficients G^{(b)}_l = int g (p-u)^b He_l(p) dp, b=0..3, l<=L
+template <int LMAX>
+__host__ __device__ inline void hermite_coeffs(double u, double T, int L, double G[4][LMAX + 4]) {
+  G[0][0] = 1.0;
+  G[0][1] = u;
+  for (int l = 1; l < L + 3; l++) G[0][l + 1] = u * G[0][l] + l * (T - 1.0) * G[0][l - 1];
+  for (int b = 1; b < 4; b++)
+    for (int l = 0; l <= L + 3 - b; l++)
+      G[b][l] = G[b - 1][l + 1] + (l > 0 ? l * G[b - 1][l - 1] : 0.0) - u * G[b - 1][l];
+}
+
+// Host-side full table of the half-range projection of g (p-u)^a (both halves,
+// 2qh entries, positive half first) -- used for the wall Maxwellians.
+inline void host_half_table(const double *lat, const LatOff &lo, int qh, double u, double T, int a,
+                            double *X) {
+  double rsT = 1.0 / sqrt(T);
+  for (int side = 0; side < 2; side++) {
+    double us = side == 0 ? u : -u;
+    double G[NB], mb[3] = {0, 0, 0};
+    for (int m = 0; m < NB; m++) G[m] = base_weight(lat, lo, m, us, T, rsT);
+    for (int m = 0; m < NB; m++) {
+      double d = lat[lo.bP + m] - us, h = lat[lo.hQ + m] * G[m];
+      mb[0] += h; mb[1] += h * d; mb[2] += h * d * d;
+    }
+    for (int k = 0; k < qh; k++) {
+      double x0 = 0;
+      for (int m = 0; m < NB; m++) x0 += G[m] * lat[lo.lam + k * NB + m];
+      double dk = lat[lo.px + k] - us, ck = lat[lo.ck + k];
+      double v;
+      if (a == 0) v = x0;
+      else if (a == 1) v = dk * x0 + ck * mb[0];
+      else if (a == 2) v = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
+      else v = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
+      X[side * qh + k] = (side == 1 && (a & 1)) ? -v : v;
+    }
+  }
+}
+
+inline void host_full_table(const double *H, int q, double u, double T, int b, double *Y) {
+  double G[4][MAXQY + 4];
+  hermite_coeffs<MAXQY>(u, T, q - 1, G);
+  for (int k = 0; k < q; k++) {
+    double s = 0;
+    for (int l = 0; l < q; l++) s += H[k * q + l] * G[b][l];
+    Y[k] = s;
+  }
+}
+
+}  // namespace fdlb

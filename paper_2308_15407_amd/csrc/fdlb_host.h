@@ -1,0 +1,55 @@
+// fdlb_host.h -- host-side structures of the FDLB solver (not part of the C ABI).
+#pragma once
+#include <string>
+#include <vector>
+
+#include "../../include/fdlb.h"
+#include "fdlb_common.h"
+
+namespace fdlb {
+
+// Host copy of one case: parameters, lattice constants, grid and wall tables.
+struct CaseHost {
+  fdlb_params p;
+  int nx, qh, qy, qz, K;
+  double sigma, R, Lc, chi0, deta, dt;
+  LatOff lo;
+  std::vector<double> lat;          // lattice constants (see LatOff)
+  std::vector<double> wx, wy, wz;   // 1D weights
+  std::vector<double> x, jac, invdx;
+  std::vector<double> gw[2];        // wall Maxwellians (n = 1) [K]
+  double wallD[2];
+  int kxc, nchunk;                  // kx per velocity chunk, number of chunks
+  size_t ws_off[32];                // workspace offsets of this case's arrays
+  int prec;                         // active storage precision
+  bool active;
+  long steps;
+  double last_resid;
+};
+
+int validate(const fdlb_params &p, std::string &why, double *sigma, double *R);
+int build_case(const fdlb_params &p, CaseHost &c, std::string &why);
+
+// table-pass mode bits
+enum {
+  TM_PARTIALS = 1,  // moments from the partial raw sums
+  TM_FIELDS = 2,    // moments from the staged Grad-13 fields (initial state)
+  TM_WRITE_MOM = 4, // store the moments of owned cells
+  TM_RESID = 8,     // residual against the stored moments
+  TM_TABLES = 16,   // projection tables for the update pass
+  TM_WALLS = 32     // wall densities (wall blocks)
+};
+
+// kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
+hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
+                        hipStream_t s);
+hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
+                         hipStream_t s);
+hipError_t launch_fill(int prec, const CaseDev *cases, const int *map, int nblocks, int waves, int use_noise,
+                       hipStream_t s);
+hipError_t launch_partials(int prec, const CaseDev *cases, const int *map, int nblocks, int waves,
+                           hipStream_t s);
+hipError_t launch_zero_resid(const CaseDev *cases, int ncases, hipStream_t s);
+hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStream_t s);
+
+}  // namespace fdlb

@@ -1,0 +1,628 @@
+// fdlb_kernels.hip -- gfx950 kernels of one FDLB stage (Sec. III.B).
+//
+// A stage is two launches over a flat block map that may span many cases:
+//   k_table  : per cell (32-cell tiles): moments of the stage input from the
+//              partial raw sums, closure (eq:chi, eq:viscosity, eq:tau,
+//              eq:prandtl), 6th-order gradients (Sec. III.B.3), the
+//              Shakhov/J1 polynomial (eq:j0, eq:j1) and its per-axis lattice
+//              projections (eq:hh_gk, eq:H_gk) written as tables n X_a[kx] and
+//              YZ_a[ky,kz]; two extra blocks per case reduce the incoming wall
+//              fluxes into the wall densities (impenetrability, Sec. III.B).
+//   k_update : per (63-cell tile, kx chunk): one 64-lane wave per y-line of
+//              velocities, lanes along cells (coalesced f[kappa][cell]); each
+//              lane reconstructs one face by WENO-5 (eq:weno5_flux_x ..
+//              eq:weno5_sigma) and takes its right neighbour's face by a lane
+//              shuffle, adds the body force (eq:kernel_H) and the relaxation to
+//              the target, applies the RK3 combination (eq:rk3) and
+//              accumulates the FP64 raw moment sums of its output, reduced
+//              across the block's waves in LDS into per-chunk partials.
+#include <hip/hip_runtime.h>
+
+#include "fdlb_common.h"
+#include "fdlb_host.h"
+
+namespace fdlb {
+
+// ---------------------------------------------------------------------------
+// small device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double fast_rcp(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+template <typename T>
+__device__ __forceinline__ T weno_face(const T v0, const T v1, const T v2, const T v3, const T v4, int mode) {
+  // candidates (eq:weno5_flux_x), upwind frame
+  const T F1 = v0 * (T)(1.0 / 3.0) - v1 * (T)(7.0 / 6.0) + v2 * (T)(11.0 / 6.0);
+  if (mode == 2) return F1;
+  const T F2 = -v1 * (T)(1.0 / 6.0) + v2 * (T)(5.0 / 6.0) + v3 * (T)(1.0 / 3.0);
+  const T F3 = v2 * (T)(1.0 / 3.0) + v3 * (T)(5.0 / 6.0) - v4 * (T)(1.0 / 6.0);
+  // smoothness indicators (eq:weno5_sigma)
+  const T a1 = v0 - (T)2 * v1 + v2, c1 = v0 - (T)4 * v1 + (T)3 * v2;
+  const T a2 = v1 - (T)2 * v2 + v3, c2 = v1 - v3;
+  const T a3 = v2 - (T)2 * v3 + v4, c3 = (T)3 * v2 - (T)4 * v3 + v4;
+  const T b1 = (T)(13.0 / 12.0) * a1 * a1 + (T)0.25 * c1 * c1;
+  const T b2 = (T)(13.0 / 12.0) * a2 * a2 + (T)0.25 * c2 * c2;
+  const T b3 = (T)(13.0 / 12.0) * a3 * a3 + (T)0.25 * c3 * c3;
+  const bool drop3 = (mode == 1);
+  const T d1 = (T)0.1, d2 = (T)0.6, d3 = drop3 ? (T)0 : (T)0.3;
+  const T bmax = drop3 ? fmax(b1, b2) : fmax(fmax(b1, b2), b3);
+  T w1, w2, w3;
+  if (bmax == (T)0) {
+    // all indicators vanish: ideal weights
+    w1 = d1; w2 = d2; w3 = d3;
+  } else {
+    // w_q ~ d_q / b_q^2, written as d_q prod_{r != q} t_r^2 with t = b / max b
+    const T r = fast_rcp(bmax);
+    const T t1 = b1 * r, t2 = b2 * r, t3 = drop3 ? (T)1 : b3 * r;
+    const T p12 = t1 * t2, p13 = t1 * t3, p23 = t2 * t3;
+    w1 = d1 * p23 * p23; w2 = d2 * p13 * p13; w3 = d3 * p12 * p12;
+    if (w1 + w2 + w3 == (T)0) {
+      // two or more indicators vanish exactly (or the products underflow):
+      // weight the zero-indicator candidates by their ideal weights, else take
+      // the smoothest candidate
+      const bool z1 = b1 == (T)0, z2 = b2 == (T)0, z3 = !drop3 && b3 == (T)0;
+      if (z1 || z2 || z3) {
+        w1 = z1 ? d1 : (T)0; w2 = z2 ? d2 : (T)0; w3 = z3 ? d3 : (T)0;
+      } else {
+        const bool m1 = b1 <= b2 && (drop3 || b1 <= b3);
+        const bool m2 = !m1 && (drop3 || b2 <= b3);
+        w1 = m1 ? (T)1 : (T)0; w2 = m2 ? (T)1 : (T)0; w3 = (!m1 && !m2) ? (T)1 : (T)0;
+      }
+    }
+  }
+  const T s = fast_rcp(w1 + w2 + w3);
+  return (w1 * F1 + w2 * F2 + w3 * F3) * s;
+}
+
+__device__ __forceinline__ double chi_cs(double eta) {
+  const double om = 1.0 - eta;
+  return 0.5 * (2.0 - eta) / (om * om * om);
+}
+
+// ---------------------------------------------------------------------------
+// table pass
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ void wall_block(const CaseDev &c, int wall, int gin) {
+  // impenetrability: the numerical mass flux through the wall face vanishes.
+  // Incoming populations reach the face through the fully interior third-order
+  // candidate; emitted ones carry n_w g^w.
+  __shared__ double red[256];
+  const T *g = (const T *)c.f[c.prec][gin];
+  const int nx = c.nx, qh = c.qh, qyz = c.qyz;
+  double acc = 0;
+  const int n_in = qh * qyz;
+  for (int t = threadIdx.x; t < n_in; t += blockDim.x) {
+    const int kx = (wall == 0 ? qh : 0) + t / qyz;
+    const int kap = kx * qyz + t % qyz;
+    const double p = c.lat[c.lo.px + kx];
+    const T *row = g + (size_t)kap * nx;
+    double f0, f1, f2;
+    if (wall == 0) { f0 = row[0]; f1 = row[1]; f2 = row[2]; }
+    else { f0 = row[nx - 1]; f1 = row[nx - 2]; f2 = row[nx - 3]; }
+    acc += p * (f2 * (1.0 / 3.0) - f1 * (7.0 / 6.0) + f0 * (11.0 / 6.0));
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
+    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) c.nw[wall] = (wall == 0 ? -red[0] : red[0]) / c.wallD[wall];
+}
+
+template <typename T>
+__global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
+                                               int mode, int gin) {
+  const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[bm.x];
+  if (!c.active) return;
+  if (bm.y < 0) {
+    if (mode & TM_WALLS) wall_block<T>(c, -bm.y - 1, gin);
+    return;
+  }
+  constexpr int W = CTILE + 2 * CHALO;
+  __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy
+  __shared__ double s_l[3][W];      // ln n, ln chi, ln T
+  __shared__ double s_c[CTILE][20]; // n, ux, uy, T, invtau, C[13]...
+  __shared__ double s_G[CTILE][2][NB];
+  __shared__ double s_mb[CTILE][2][3];
+  __shared__ double s_red[256];
+  const int nx = c.nx, c0 = bm.y * CTILE;
+  const int own = min(CTILE, nx - c0);
+  const int tid = threadIdx.x;
+  const double *lat = c.lat;
+  const LatOff lo = c.lo;
+
+  // ---- moments of the stage input for the tile and its halo ----
+  double rmax = 0;
+  if (tid < W) {
+    const int cell = c0 - CHALO + tid;
+    if (cell >= 0 && cell < nx) {
+      double n, ux, uy, T_, qx, qy, pxx = 0, pxy = 0, pyy = 0, pzz = 0;
+      if (mode & TM_FIELDS) {
+        const double *fl = c.fields;
+        n = fl[cell]; ux = fl[nx + cell]; uy = fl[2 * nx + cell]; T_ = fl[3 * nx + cell];
+        qx = fl[4 * nx + cell]; qy = fl[5 * nx + cell];   // slot 5 carries P_xy
+      } else {
+        double S[NRAW];
+#pragma unroll
+        for (int m = 0; m < NRAW; m++) S[m] = 0;
+        for (int ch = 0; ch < c.nchunk; ch++) {
+          const double *pp = c.part + (size_t)ch * NRAW * nx + cell;
+#pragma unroll
+          for (int m = 0; m < NRAW; m++) S[m] += pp[(size_t)m * nx];
+        }
+        n = S[0];
+        ux = S[1] / n; uy = S[2] / n;
+        pxx = S[3] - n * ux * ux; pxy = S[4] - n * ux * uy; pyy = S[5] - n * uy * uy; pzz = S[6];
+        const double S2 = S[3] + S[5] + S[6], u2 = ux * ux + uy * uy;
+        T_ = (pxx + pyy + pzz) / (3.0 * n);
+        qx = 0.5 * (S[7] - 2.0 * (ux * S[3] + uy * S[4]) - ux * S2 + 2.0 * n * ux * u2);
+        qy = 0.5 * (S[8] - 2.0 * (ux * S[4] + uy * S[5]) - uy * S2 + 2.0 * n * uy * u2);
+      }
+      s_m[0][tid] = n; s_m[1][tid] = ux; s_m[2][tid] = uy; s_m[3][tid] = T_; s_m[4][tid] = qx; s_m[5][tid] = qy;
+      s_l[0][tid] = log(n); s_l[1][tid] = log(chi_cs(c.eta0 * n)); s_l[2][tid] = log(T_);
+      const bool owned = tid >= CHALO && tid < CHALO + own;
+      if (owned && (mode & TM_RESID)) {
+        const double *mo = c.mom;
+        const double dn = fabs(n - mo[cell]), dux = fabs(ux - mo[nx + cell]);
+        const double duy = fabs(uy - mo[2 * nx + cell]), dT = fabs(T_ - mo[3 * nx + cell]);
+        double r = fmax(fmax(dn, dux), fmax(duy, dT)) / c.dt;
+        if (!(n > 0.0) || !(T_ > 0.0) || !isfinite(r) || !isfinite(qx) || !isfinite(qy)) r = __longlong_as_double(0x7ff8000000000000LL);
+        rmax = r;
+      }
+      if (owned && (mode & TM_WRITE_MOM)) {
+        double *mo = c.mom;
+        mo[cell] = n; mo[nx + cell] = ux; mo[2 * nx + cell] = uy; mo[3 * nx + cell] = T_;
+        mo[4 * nx + cell] = qx; mo[5 * nx + cell] = qy; mo[6 * nx + cell] = pxx;
+        mo[7 * nx + cell] = pxy; mo[8 * nx + cell] = pyy; mo[9 * nx + cell] = pzz;
+      }
+    }
+  }
+  if (mode & TM_RESID) {
+    s_red[tid] = rmax;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+      if (tid < s) {
+        const double a = s_red[tid], b = s_red[tid + s];
+        s_red[tid] = (a != a || b != b) ? __longlong_as_double(0x7ff8000000000000LL) : fmax(a, b);
+      }
+      __syncthreads();
+    }
+    if (tid == 0) atomicMax(c.resid, (unsigned long long)__double_as_longlong(s_red[0]));
+  }
+  if (!(mode & TM_TABLES)) return;
+  __syncthreads();
+
+  // ---- closure, gradients and the target polynomial per owned cell ----
+  if (tid < own) {
+    const int i = c0 + tid, li = tid + CHALO;
+    const double n = s_m[0][li], ux = s_m[1][li], uy = s_m[2][li], T_ = s_m[3][li];
+    double C[13];
+    double itau = 0.0;
+    if (mode & TM_FIELDS) {
+      // Grad-13-type state: 1 + Pxy xi_x xi_y/(n T^2) + qx xi_x (xi^2/T - 5)/(5 n T^2)
+      const double qx = s_m[4][li], pxy = s_m[5][li];
+      const double nT2 = n * T_ * T_;
+      for (int q = 0; q < 13; q++) C[q] = 0.0;
+      C[0] = 1.0;
+      C[1] = -qx / nT2;
+      C[6] = pxy / nT2;
+      C[7] = qx / (5.0 * nT2 * T_);
+      C[8] = C[7];
+      C[9] = C[7];
+    } else {
+      // gradients d/dx = (d/deta)/J, 6th-order central inside, one-sided at walls
+      double g[5];
+      const double *fw = lat + lo.fdw;
+      for (int q = 0; q < 5; q++) {
+        const double *src = q == 0 ? s_l[0] : (q == 1 ? s_l[1] : (q == 2 ? s_l[2] : (q == 3 ? s_m[1] : s_m[2])));
+        double d;
+        if (i >= 3 && i <= nx - 4) {
+          d = (src[li + 1] - src[li - 1]) * 0.75 - (src[li + 2] - src[li - 2]) * 0.15 +
+              (src[li + 3] - src[li - 3]) * (1.0 / 60.0);
+        } else if (i < 3) {
+          d = 0;
+          for (int jj = 0; jj < 7; jj++) d += fw[i * 7 + jj] * src[li - i + jj];
+        } else {
+          const int r = nx - 1 - i;
+          d = 0;
+          for (int jj = 0; jj < 7; jj++) d -= fw[r * 7 + jj] * src[li + r - jj];
+        }
+        g[q] = d * c.invdx[i];
+      }
+      const double eta = c.eta0 * n, chi = chi_cs(eta);
+      const double brc = 4.0 * eta * chi;   // b rho chi
+      double tau = 0.0;
+      if (c.tau_pre > 0.0) {
+        tau = c.tau_pre / (n * sqrt(T_)) *
+              (1.0 / chi + 3.2 * eta + 64.0 / 25.0 * (1.0 + 12.0 / M_PI) * eta * eta * chi);
+        itau = 1.0 / tau;
+      }
+      double Pr = 1.0;
+      if (c.collision == 1) Pr = c.pr_fixed;
+      else if (c.collision == 2)
+        Pr = 2.0 / 3.0 * (1.0 + 0.8 * brc + 4.0 / 25.0 * (1.0 + 12.0 / M_PI) * brc * brc) /
+             (1.0 + 1.2 * brc + 9.0 / 25.0 * (1.0 + 32.0 / (9.0 * M_PI)) * brc * brc);
+      const double qx = s_m[4][li], qy = s_m[5][li];
+      const double s0 = (1.0 - Pr) / (n * T_ * T_);
+      const double A = -tau * brc;                  // tau J1 prefactor
+      const double D = 2.0 * g[0] + g[1] + g[2];    // d ln(rho^2 chi T)/dx
+      const double G = g[2], dux = g[3], duy = g[4];
+      const double iT = 1.0 / T_;
+      // coefficients of xi_x^a xi_y^b xi_z^c in 1 + S + tau J:
+      // 0:000 1:100 2:010 3:200 4:020 5:002 6:110 7:300 8:120 9:102 10:210 11:030 12:012
+      C[0] = 1.0 - A * dux;
+      C[1] = A * (D - 1.5 * G) - s0 * qx;
+      C[2] = -s0 * qy;
+      C[3] = A * 0.6 * dux * iT;
+      C[4] = A * 0.2 * dux * iT;
+      C[5] = C[4];
+      C[6] = A * 0.4 * (c.j1_shear ? duy : 0.0) * iT;
+      C[7] = A * 0.3 * G * iT + 0.2 * s0 * qx * iT;
+      C[8] = C[7];
+      C[9] = C[7];
+      C[10] = 0.2 * s0 * qy * iT;
+      C[11] = C[10];
+      C[12] = C[10];
+    }
+    s_c[tid][0] = n; s_c[tid][1] = ux; s_c[tid][2] = uy; s_c[tid][3] = T_; s_c[tid][4] = itau;
+    for (int q = 0; q < 13; q++) s_c[tid][5 + q] = C[q];
+  }
+  __syncthreads();
+
+  // ---- half-range base weights per owned cell and half ----
+  for (int it = tid; it < own * 2 * NB; it += blockDim.x) {
+    const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
+    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1], T_ = s_c[cl][3];
+    s_G[cl][h][m] = base_weight(lat, lo, m, u, T_, 1.0 / sqrt(T_));
+  }
+  __syncthreads();
+  for (int it = tid; it < own * 2; it += blockDim.x) {
+    const int cl = it >> 1, h = it & 1;
+    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
+    double m0 = 0, m1 = 0, m2 = 0;
+    for (int m = 0; m < NB; m++) {
+      const double d = lat[lo.bP + m] - u, hv = lat[lo.hQ + m] * s_G[cl][h][m];
+      m0 += hv; m1 += hv * d; m2 += hv * d * d;
+    }
+    s_mb[cl][h][0] = m0; s_mb[cl][h][1] = m1; s_mb[cl][h][2] = m2;
+  }
+  __syncthreads();
+
+  // ---- n X_a[kx] tables ----
+  const int nkx = c.nkx, qh = c.qh;
+  T *tX = (T *)c.tabX[c.prec];
+  for (int it = tid; it < own * nkx; it += blockDim.x) {
+    const int cl = it % own, kx = it / own;     // cell fastest: coalesced stores
+    const int h = kx >= qh, k = kx - h * qh;
+    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
+    double x0 = 0;
+    const double *lam = lat + lo.lam + k * NB;
+    for (int m = 0; m < NB; m++) x0 += s_G[cl][h][m] * lam[m];
+    const double dk = lat[lo.px + k] - u, ck = lat[lo.ck + k];
+    const double *mb = s_mb[cl][h];
+    const double X1 = dk * x0 + ck * mb[0];
+    const double X2 = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
+    const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
+    const double sg = h ? -1.0 : 1.0, n = s_c[cl][0];
+    const size_t i = (size_t)c0 + cl;
+    tX[(size_t)(0 * nkx + kx) * nx + i] = (T)(n * x0);
+    tX[(size_t)(1 * nkx + kx) * nx + i] = (T)(n * sg * X1);
+    tX[(size_t)(2 * nkx + kx) * nx + i] = (T)(n * X2);
+    tX[(size_t)(3 * nkx + kx) * nx + i] = (T)(n * sg * X3);
+  }
+
+  // ---- YZ_a[ky,kz] tables and 1/tau ----
+  const int qy = c.qy, qz = c.qz, qyz = c.qyz;
+  T *tYZ = (T *)c.tabYZ[c.prec];
+  for (int it = tid; it < own * qyz; it += blockDim.x) {
+    const int cl = it % own, yz = it / own, ky = yz / qz, kz = yz % qz;
+    const double uy = s_c[cl][2], T_ = s_c[cl][3];
+    double G[4][MAXQY + 4];
+    hermite_coeffs<MAXQY>(uy, T_, qy - 1, G);
+    double Y[4] = {0, 0, 0, 0};
+    const double *Hy = lat + lo.Hy + ky * qy;
+    for (int l = 0; l < qy; l++) {
+      Y[0] += Hy[l] * G[0][l]; Y[1] += Hy[l] * G[1][l]; Y[2] += Hy[l] * G[2][l]; Y[3] += Hy[l] * G[3][l];
+    }
+    hermite_coeffs<MAXQY>(0.0, T_, qz - 1, G);
+    double Z0 = 0, Z2 = 0;
+    const double *Hz = lat + lo.Hz + kz * qz;
+    for (int l = 0; l < qz; l++) { Z0 += Hz[l] * G[0][l]; Z2 += Hz[l] * G[2][l]; }
+    const double *C = &s_c[cl][5];
+    const double yz0 = C[0] * Y[0] * Z0 + C[2] * Y[1] * Z0 + C[4] * Y[2] * Z0 + C[11] * Y[3] * Z0 +
+                       C[5] * Y[0] * Z2 + C[12] * Y[1] * Z2;
+    const double yz1 = C[1] * Y[0] * Z0 + C[6] * Y[1] * Z0 + C[8] * Y[2] * Z0 + C[9] * Y[0] * Z2;
+    const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
+    const double yz3 = C[7] * Y[0] * Z0;
+    const size_t i = (size_t)c0 + cl;
+    tYZ[(size_t)(0 * qyz + yz) * nx + i] = (T)yz0;
+    tYZ[(size_t)(1 * qyz + yz) * nx + i] = (T)yz1;
+    tYZ[(size_t)(2 * qyz + yz) * nx + i] = (T)yz2;
+    tYZ[(size_t)(3 * qyz + yz) * nx + i] = (T)yz3;
+  }
+  if (tid < own) ((T *)c.invtau[c.prec])[c0 + tid] = (T)s_c[tid][4];
+}
+
+// ---------------------------------------------------------------------------
+// update pass
+// ---------------------------------------------------------------------------
+template <typename T>
+__device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int c0, double (&acc)[NRAW],
+                                               bool is_cell) {
+  __shared__ double s_acc[8][NRAW][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+#pragma unroll
+  for (int m = 0; m < NRAW; m++) s_acc[wv][m][lane] = acc[m];
+  __syncthreads();
+  for (int it = threadIdx.x; it < NRAW * 64; it += blockDim.x) {
+    const int m = it / 64, l = it % 64;
+    const int cell = c0 + l;
+    if (l < UTILE && cell < c.nx) {
+      double s = 0;
+      for (int w = 0; w < nwv; w++) s += s_acc[w][m][l];
+      c.part[((size_t)chunk * NRAW + m) * c.nx + cell] = s;
+    }
+  }
+  (void)is_cell;
+}
+
+template <typename T, int STAGE>
+__global__ void __launch_bounds__(512) k_update(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
+  const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[bm.x];
+  if (!c.active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int nx = c.nx, qy = c.qy, qz = c.qz, qyz = c.qyz, nkx = c.nkx;
+  const int P = c.prec;
+  const T *__restrict__ gin = (const T *)c.f[P][STAGE == 1 ? 0 : (STAGE == 2 ? 1 : 2)];
+  // stage 3 writes f^{n+1} over f^n: each lane reads f^n only at the node it writes
+  const T *fn = (const T *)c.f[P][0];
+  T *out = (T *)c.f[P][STAGE == 1 ? 1 : (STAGE == 2 ? 2 : 0)];
+  const T *__restrict__ tX = (const T *)c.tabX[P];
+  const T *__restrict__ tYZ = (const T *)c.tabYZ[P];
+  const T *__restrict__ gwL = (const T *)c.gw[P][0];
+  const T *__restrict__ gwR = (const T *)c.gw[P][1];
+  const double *__restrict__ lat = c.lat;
+  const int c0 = bm.y * UTILE;
+  const int j = c0 + lane;                       // face j (left face of cell j)
+  const bool is_cell = lane < UTILE && j < nx;
+  const int jc = min(j, nx - 1);
+  const int kx0 = bm.z * c.kxc, kx1 = min(kx0 + c.kxc, nkx);
+  const double nwl = c.nw[0], nwr = c.nw[1];
+  const T dxi = (T)c.invdx[jc];
+  const T itau = ((const T *)c.invtau[P])[jc];
+  const T dt = (T)c.dt, ay = (T)c.ay;
+  const bool force = c.ay != 0.0;
+  double acc[NRAW];
+#pragma unroll
+  for (int m = 0; m < NRAW; m++) acc[m] = 0.0;
+
+  const int nlines = (kx1 - kx0) * qz;
+  for (int line = wv; line < nlines; line += nwv) {
+    const int kx = kx0 + line / qz, kz = line - (line / qz) * qz;
+    const double pxd = lat[c.lo.px + kx];
+    const bool pos = pxd > 0.0;
+    const T px = (T)pxd;
+    const double pzd = lat[c.lo.pz + kz];
+    int mode;
+    if (pos) mode = (j == 0) ? 3 : (j == nx ? 2 : (j == nx - 1 ? 1 : 0));
+    else mode = (j == nx) ? 3 : (j == 0 ? 2 : (j == 1 ? 1 : 0));
+    const T X0 = tX[(size_t)(0 * nkx + kx) * nx + jc], X1 = tX[(size_t)(1 * nkx + kx) * nx + jc];
+    const T X2 = tX[(size_t)(2 * nkx + kx) * nx + jc], X3 = tX[(size_t)(3 * nkx + kx) * nx + jc];
+    T cen[MAXQY], adv[MAXQY];
+#pragma unroll
+    for (int ky = 0; ky < MAXQY; ky++) {
+      if (ky < qy) {
+        const int kap = (kx * qy + ky) * qz + kz;
+        const T *row = gin + (size_t)kap * nx;
+        const T fw = (T)((pos ? nwl : nwr) * (double)(pos ? gwL[kap] : gwR[kap]));
+        T v[5];
+#pragma unroll
+        for (int s = 0; s < 5; s++) {
+          const int ci = pos ? j - 3 + s : j + 2 - s;
+          const int cc = min(max(ci, 0), nx - 1);
+          const T val = row[cc];
+          v[s] = (ci < 0 || ci >= nx) ? fw : val;
+        }
+        const T fh = (mode == 3) ? fw : weno_face<T>(v[0], v[1], v[2], v[3], v[4], mode);
+        const T fr = __shfl_down(fh, 1, 64);
+        cen[ky] = pos ? v[3] : v[2];
+        adv[ky] = -px * dxi * (fr - fh);
+      }
+    }
+#pragma unroll
+    for (int ky = 0; ky < MAXQY; ky++) {
+      if (ky < qy) {
+        const int kap = (kx * qy + ky) * qz + kz;
+        const int yz = ky * qz + kz;
+        T L = adv[ky];
+        if (force) {
+          T s = 0;
+          const double *km = lat + c.lo.kmat + ky * qy;
+#pragma unroll
+          for (int k2 = 0; k2 < MAXQY; k2++)
+            if (k2 < qy) s += (T)km[k2] * cen[k2];
+          L -= ay * s;
+        }
+        const T F = X0 * tYZ[(size_t)(0 * qyz + yz) * nx + jc] + X1 * tYZ[(size_t)(1 * qyz + yz) * nx + jc] +
+                    X2 * tYZ[(size_t)(2 * qyz + yz) * nx + jc] + X3 * tYZ[(size_t)(3 * qyz + yz) * nx + jc];
+        L += (F - cen[ky]) * itau;
+        const T adv1 = cen[ky] + dt * L;
+        T o;
+        if (STAGE == 1) o = adv1;
+        else {
+          const T fnv = fn[(size_t)kap * nx + jc];
+          o = (STAGE == 2) ? (T)0.75 * fnv + (T)0.25 * adv1 : fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
+        }
+        if (is_cell) {
+          out[(size_t)kap * nx + j] = o;
+          const double od = (double)o, pyd = lat[c.lo.py + ky];
+          const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
+          acc[0] += od;
+          acc[1] += pxd * od;
+          acc[2] += pyd * od;
+          acc[3] += pxd * pxd * od;
+          acc[4] += pxd * pyd * od;
+          acc[5] += pyd * pyd * od;
+          acc[6] += pzd * pzd * od;
+          acc[7] += pxd * p2 * od;
+          acc[8] += pyd * p2 * od;
+        }
+      }
+    }
+  }
+  block_partials<T>(c, bm.z, c0, acc, is_cell);
+}
+
+// initial state from the tables: f = sum_a n X_a YZ_a (times 1 + noise)
+template <typename T>
+__global__ void __launch_bounds__(512) k_fill(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
+                                              int use_noise) {
+  const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[bm.x];
+  if (!c.active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int nx = c.nx, qy = c.qy, qz = c.qz, qyz = c.qyz, nkx = c.nkx, P = c.prec;
+  T *f = (T *)c.f[P][0];
+  const T *tX = (const T *)c.tabX[P];
+  const T *tYZ = (const T *)c.tabYZ[P];
+  const double *lat = c.lat;
+  const int c0 = bm.y * UTILE, j = c0 + lane;
+  const bool is_cell = lane < UTILE && j < nx;
+  const int jc = min(j, nx - 1);
+  const int kx0 = bm.z * c.kxc, kx1 = min(kx0 + c.kxc, nkx);
+  double acc[NRAW];
+  for (int m = 0; m < NRAW; m++) acc[m] = 0.0;
+  const int nrows = (kx1 - kx0) * qyz;
+  for (int r = wv; r < nrows; r += nwv) {
+    const int kx = kx0 + r / qyz, yz = r % qyz, ky = yz / qz, kz = yz % qz;
+    const int kap = kx * qyz + yz;
+    double F = 0;
+    for (int a = 0; a < 4; a++)
+      F += (double)tX[(size_t)(a * nkx + kx) * nx + jc] * (double)tYZ[(size_t)(a * qyz + yz) * nx + jc];
+    if (use_noise) F *= 1.0 + c.noise[(size_t)kap * nx + jc];
+    const T o = (T)F;
+    if (is_cell) {
+      f[(size_t)kap * nx + j] = o;
+      const double od = (double)o, pxd = lat[c.lo.px + kx], pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
+      const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
+      acc[0] += od; acc[1] += pxd * od; acc[2] += pyd * od; acc[3] += pxd * pxd * od; acc[4] += pxd * pyd * od;
+      acc[5] += pyd * pyd * od; acc[6] += pzd * pzd * od; acc[7] += pxd * p2 * od; acc[8] += pyd * p2 * od;
+    }
+  }
+  block_partials<T>(c, bm.z, c0, acc, is_cell);
+}
+
+// partial raw sums of f^n (after an upload)
+template <typename T>
+__global__ void __launch_bounds__(512) k_partials(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
+  const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[bm.x];
+  if (!c.active) return;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
+  const int nx = c.nx, qz = c.qz, qyz = c.qyz, nkx = c.nkx, P = c.prec;
+  const T *f = (const T *)c.f[P][0];
+  const double *lat = c.lat;
+  const int c0 = bm.y * UTILE, j = c0 + lane;
+  const bool is_cell = lane < UTILE && j < nx;
+  const int jc = min(j, nx - 1);
+  const int kx0 = bm.z * c.kxc, kx1 = min(kx0 + c.kxc, nkx);
+  double acc[NRAW];
+  for (int m = 0; m < NRAW; m++) acc[m] = 0.0;
+  const int nrows = (kx1 - kx0) * qyz;
+  for (int r = wv; r < nrows; r += nwv) {
+    const int kx = kx0 + r / qyz, yz = r % qyz, ky = yz / qz, kz = yz % qz;
+    const int kap = kx * qyz + yz;
+    if (is_cell) {
+      const double od = (double)f[(size_t)kap * nx + jc];
+      const double pxd = lat[c.lo.px + kx], pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
+      const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
+      acc[0] += od; acc[1] += pxd * od; acc[2] += pyd * od; acc[3] += pxd * pxd * od; acc[4] += pxd * pyd * od;
+      acc[5] += pyd * pyd * od; acc[6] += pzd * pzd * od; acc[7] += pxd * p2 * od; acc[8] += pyd * p2 * od;
+    }
+  }
+  block_partials<T>(c, bm.z, c0, acc, is_cell);
+}
+
+__global__ void k_zero_resid(const CaseDev *__restrict__ cases, int ncases) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < ncases) *cases[i].resid = 0ull;
+}
+
+template <typename S, typename D>
+__global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    dst[i] = (D)src[i];
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
+                        hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_table<double>, dim3(nblocks), dim3(256), 0, s, cases, (const int4 *)map, mode, gin);
+  else
+    hipLaunchKernelGGL(k_table<float>, dim3(nblocks), dim3(256), 0, s, cases, (const int4 *)map, mode, gin);
+  return hipGetLastError();
+}
+
+template <typename T>
+static void upd(int stage, dim3 g, dim3 b, hipStream_t s, const CaseDev *cases, const int4 *map) {
+  if (stage == 1) hipLaunchKernelGGL((k_update<T, 1>), g, b, 0, s, cases, map);
+  else if (stage == 2) hipLaunchKernelGGL((k_update<T, 2>), g, b, 0, s, cases, map);
+  else hipLaunchKernelGGL((k_update<T, 3>), g, b, 0, s, cases, map);
+}
+
+hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
+                         hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (prec == 0) upd<double>(stage, dim3(nblocks), dim3(64 * waves), s, cases, (const int4 *)map);
+  else upd<float>(stage, dim3(nblocks), dim3(64 * waves), s, cases, (const int4 *)map);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill(int prec, const CaseDev *cases, const int *map, int nblocks, int waves, int use_noise,
+                       hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_fill<double>, dim3(nblocks), dim3(64 * waves), 0, s, cases, (const int4 *)map, use_noise);
+  else
+    hipLaunchKernelGGL(k_fill<float>, dim3(nblocks), dim3(64 * waves), 0, s, cases, (const int4 *)map, use_noise);
+  return hipGetLastError();
+}
+
+hipError_t launch_partials(int prec, const CaseDev *cases, const int *map, int nblocks, int waves, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (prec == 0)
+    hipLaunchKernelGGL(k_partials<double>, dim3(nblocks), dim3(64 * waves), 0, s, cases, (const int4 *)map);
+  else
+    hipLaunchKernelGGL(k_partials<float>, dim3(nblocks), dim3(64 * waves), 0, s, cases, (const int4 *)map);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_resid(const CaseDev *cases, int ncases, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_resid, dim3((ncases + 255) / 256), dim3(256), 0, s, cases, ncases);
+  return hipGetLastError();
+}
+
+// dir 0: float -> double, dir 1: double -> float
+hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStream_t s) {
+  const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  if (n == 0) return hipSuccess;
+  if (dir == 0)
+    hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks), dim3(256), 0, s, (const float *)src, (double *)dst, n);
+  else
+    hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks), dim3(256), 0, s, (const double *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
+}  // namespace fdlb
