@@ -1,0 +1,158 @@
+"""Benchmark: node-velocity updates per second of the FDLB time step on one MI355X.
+
+Workload (default): the plain Couette configuration -- Nx = 256 wall-refined
+cells, 2x8 half-range x 4 x 4 full-range velocities (K = 256), Kn = 0.1,
+eta0 = 0.2, walls T = 1 moving at u_y = -/+0.2, Shakhov Pr = 2/3, FP64.  One
+step = one TVD-RK3 step (three stages of table + update launches) of the whole
+case; inputs are resident in device memory before timing starts.
+
+Also reported: the FP32-bulk variant of the same case, a large single case
+(Nx = 32768, K = 512) that sizes the memory-bound roofline, the roofline
+object for the dominant kernel (the update launch of RK stage 2) with its
+time measured by HIP events, and the CPU oracle timed on this host.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--no-extra", action="store_true", help="only the main workload")
+    ap.add_argument("--large-steps", type=int, default=60)
+    ap.add_argument("--retune", action="store_true")
+    return ap.parse_args()
+
+
+def kernel_src_hash():
+    h = hashlib.sha1()
+    for f in ("fdlb_kernels.hip", "fdlb_common.h"):
+        h.update(open(os.path.join(ROOT, "paper_2308_15407_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:12]
+
+
+def read_traffic(kernel, workload):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "traffic_counters.md")
+    if not os.path.exists(path):
+        return None
+    for line in open(path):
+        parts = line.split()
+        if len(parts) >= 6 and parts[0] == "TRAFFIC" and parts[1] == kernel and parts[2] == workload:
+            if parts[3] != kernel_src_hash():
+                return None
+            return float(parts[4]) + float(parts[5])
+    return None
+
+
+def timed_run(solver, steps, warmup):
+    import torch
+    solver.step(warmup)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(solver.stream)
+    solver.step(steps)
+    b.record(solver.stream)
+    b.synchronize()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def measure(cfg, steps, warmup, retune, graph_steps=50):
+    from paper_2308_15407_amd.solver import Solver
+    from paper_2308_15407_amd import autotune
+    s = Solver(cfg)
+    tile = autotune.tune(s, use_cache=not retune)
+    s.set_graph_steps(graph_steps)
+    ms = timed_run(s, steps, warmup)
+    nodes = cfg["nx"] * 2 * cfg["qx_half"] * cfg["qy"] * cfg["qz"]
+    prof = s.profile(nrep=20)
+    return s, ms, nodes, tile, prof
+
+
+def roofline(prof, nodes, prec, kernel_name, workload):
+    """Dominant kernel: the stage-2 update (reads f^(1) and f^n, writes f^(2)):
+    3 passes x bytes per population x nodes, algorithmic."""
+    s_bytes = 8 if prec == 0 else 4
+    t_ms = prof[2] if prec == 0 else prof[5]
+    alg = 3.0 * s_bytes * nodes
+    achieved = alg / (t_ms * 1e-3) / 1e9
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(kernel_name, workload),
+            "kernel": kernel_name, "launch_ms": round(t_ms, 5), "algorithmic_bytes_per_launch": alg}
+
+
+def cpu_baseline(cfg, budget_s=15.0):
+    from oracle import oracle as O
+    o = O.Oracle(**{k: v for k, v in cfg.items() if k != "precision"})
+    t0 = time.perf_counter()
+    o.step(1)
+    one = time.perf_counter() - t0
+    n = max(1, min(2000, int(budget_s / max(one, 1e-6))))
+    t0 = time.perf_counter()
+    o.step(n)
+    dt = time.perf_counter() - t0
+    nodes = cfg["nx"] * o.K
+    return {"value": nodes * n / dt, "unit": "node-velocity updates/s", "cores": 1, "kind": "oracle",
+            "sample": "%d RK3 steps of the same case (Nx=%d, K=%d) on one host thread, %.1f s" % (n, cfg["nx"], o.K, dt)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only; this build has no multi-GPU path (got --gpus %d)" % args.gpus,
+              file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import fdlb_inputs as I
+    assert torch.cuda.is_available(), "bench.py needs a HIP device"
+    cfg = I.config(args.workload, precision=0)
+    s, ms, nodes, tile, prof = measure(cfg, args.steps, args.warmup, args.retune)
+    value = nodes / (ms * 1e-3)
+    out = {
+        "metric": "node-velocity updates/s",
+        "value": round(value, 1),
+        "unit": "node-velocity updates/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": round(ms, 6),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64", "data": "synthetic",
+        "config": {"workload": "%s Couette: Nx=256 tanh-stretched, 2x8 half-range x 4 x 4 (K=256), Kn=0.1, "
+                               "eta0=0.2, walls T=1 at u_y=-/+0.2, Shakhov Pr=2/3, FP64" % args.workload,
+                   "nodes": nodes, "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}},
+        "roofline": roofline(prof, nodes, 0, "k_update<double,2>", args.workload),
+    }
+    if not args.no_extra:
+        cfg32 = I.config(args.workload, precision=1)
+        _, ms32, _, tile32, prof32 = measure(cfg32, args.steps, args.warmup, args.retune)
+        out["fp32_bulk"] = {"value": round(nodes / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 6),
+                            "roofline": roofline(prof32, nodes, 1, "k_update<float,2>", args.workload)}
+        for prec in (0, 1):
+            cfgL = I.config("R2", precision=prec)
+            _, msL, nodesL, tileL, profL = measure(cfgL, args.large_steps, 5, args.retune, graph_steps=10)
+            out["large_case_" + ("f64" if prec == 0 else "f32")] = {
+                "workload": "Fourier Nx=32768 uniform, 2x16 x 4 x 4 (K=512), %s" % ("FP64" if prec == 0 else "FP32 bulk"),
+                "value": round(nodesL / (msL * 1e-3), 1), "ms_per_step": round(msL, 5),
+                "tiling": {"kx_per_chunk": tileL[0], "waves": tileL[1]},
+                "roofline": roofline(profL, nodesL, prec, "k_update<%s,2>" % ("double" if prec == 0 else "float"), "R2"),
+                "kernel_ms": {"table": round(profL[0], 5), "update": [round(x, 5) for x in profL[1 + 3 * prec:4 + 3 * prec]]}}
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -150,6 +150,16 @@ int fdlb_set_tiling(fdlb_handle h, int kx_per_chunk, int waves_per_block);
 /* Capture nsteps steps in a HIP graph that fdlb_step replays (0 disables). */
 int fdlb_set_graph_steps(fdlb_handle h, int nsteps);
 
+/* Measurement: average device time in ms of each kernel of one step, from
+   HIP events on the caller's stream around nrep back-to-back launches of that
+   kernel alone.  ms_out[7] = table pass, update stages 1-3 (FP64 cases),
+   update stages 1-3 (FP32-bulk cases).  Advances the state by one step. */
+int fdlb_profile(fdlb_handle h, int nrep, double *ms_out);
+
+/* Measurement: plain device-to-device copy of `bytes` (a multiple of 32) on
+   the given stream, used to calibrate hardware traffic counters. */
+int fdlb_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
+
 /* Release host-side state (the caller still owns the workspace). */
 void fdlb_destroy(fdlb_handle h);
 

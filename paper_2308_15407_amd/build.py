@@ -17,20 +17,21 @@ def hipcc():
     return "hipcc"
 
 
-def build(verbose=False):
+def build(verbose=False, out=None, defines=()):
     """Always recompiles; returns the path of the shared library."""
-    tmp = LIB + ".tmp%d" % os.getpid()
+    target = out or LIB
+    tmp = target + ".tmp%d" % os.getpid()
     cmd = [hipcc(), "--offload-arch=" + ARCH, "-O3", "-fPIC", "-shared", "-std=c++17",
            # keep FP32 arithmetic unpacked (no v_pk_*_f32)
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
            "-Wno-unused-command-line-argument",
            "-I", CSRC, "-I", os.path.join(os.path.dirname(HERE), "include"),
-           "-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
+           ] + ["-D" + d for d in defines] + ["-x", "hip"] + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", tmp]
     if verbose:
         print(" ".join(cmd), flush=True)
     subprocess.check_call(cmd)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, target)
+    return target
 
 
 if __name__ == "__main__":

@@ -43,6 +43,7 @@ struct fdlb_ctx {
   size_t map_cap = 0;         // entries available
   int *d_mapT[2] = {nullptr, nullptr}, *d_mapU[2] = {nullptr, nullptr};
   int nT[2] = {0, 0}, nU[2] = {0, 0};
+  int force[2] = {0, 0};      // some case of the group has a body force
   int waves = 4;
   int kx_user = 0;
   int graph_steps = 0;
@@ -90,7 +91,7 @@ static size_t map_entries(const std::vector<CaseHost> &cs) {
     const int nkx = 2 * c.qh;
     n += (size_t)((c.nx + CTILE - 1) / CTILE + 2) + (size_t)((c.nx + UTILE - 1) / UTILE) * nkx;
   }
-  return 2 * n;  // room for both precision groups
+  return 2 * n + 2 * 64;  // room for both precision groups and XCD padding
 }
 
 static size_t header_bytes(int ncases, size_t mapn) {
@@ -155,9 +156,26 @@ static void drop_graph(fdlb_ctx *h) {
   if (h->graph) { (void)hipGraphDestroy(h->graph); h->graph = nullptr; }
 }
 
+// Spread a block list over the 8 XCDs so that each XCD runs a contiguous
+// range of it (blocks are dispatched round-robin over XCDs): the velocity
+// chunks of one cell tile then share that XCD's L2 for the per-cell tables.
+static std::vector<int> xcd_interleave(const std::vector<int> &logical) {
+  const size_t n = logical.size() / 4;
+  if (n < 16) return logical;
+  const size_t per = (n + 7) / 8;
+  std::vector<int> phys(per * 8 * 4, 0);
+  for (size_t p = 0; p < per * 8; p++) {
+    const size_t i = (p % 8) * per + p / 8;
+    if (i < n) for (int k = 0; k < 4; k++) phys[p * 4 + k] = logical[i * 4 + k];
+    else { phys[p * 4] = -1; phys[p * 4 + 1] = 0; phys[p * 4 + 2] = 0; phys[p * 4 + 3] = 0; }
+  }
+  return phys;
+}
+
 static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
   std::vector<int> mt[2], mu[2];
+  h->force[0] = h->force[1] = 0;
   for (size_t ci = 0; ci < h->cases.size(); ci++) {
     CaseHost &c = h->cases[ci];
     CaseDev &d = h->hdev[ci];
@@ -168,13 +186,15 @@ static int build_maps(fdlb_ctx *h) {
     d.prec = c.prec;
     if (!c.active) continue;
     const int P = c.prec;
+    if (c.p.ay != 0.0) h->force[P] = 1;
     const int nct = (c.nx + CTILE - 1) / CTILE, nut = (c.nx + UTILE - 1) / UTILE;
     for (int t = 0; t < nct; t++) { mt[P].insert(mt[P].end(), {(int)ci, t, 0, 0}); }
     mt[P].insert(mt[P].end(), {(int)ci, -1, 0, 0});
     mt[P].insert(mt[P].end(), {(int)ci, -2, 0, 0});
-    for (int ch = 0; ch < c.nchunk; ch++)
-      for (int t = 0; t < nut; t++) mu[P].insert(mu[P].end(), {(int)ci, t, ch, 0});
+    for (int t = 0; t < nut; t++)
+      for (int ch = 0; ch < c.nchunk; ch++) mu[P].insert(mu[P].end(), {(int)ci, t, ch, 0});
   }
+  for (int P = 0; P < 2; P++) mu[P] = xcd_interleave(mu[P]);
   size_t need = 0;
   for (int P = 0; P < 2; P++) need += (mt[P].size() + mu[P].size()) / 4;
   if (need > h->map_cap) return fail(FDLB_ENOMEM, "launch map exceeds its reserved space");
@@ -207,7 +227,7 @@ static int launch_steps(fdlb_ctx *h, long nsteps, hipStream_t s) {
         if (h->nU[P] == 0) continue;
         int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
         HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], mode, stage - 1, s));
-        HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[P], h->nU[P], h->waves, s));
+        HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[P], h->nU[P], h->waves, h->force[P], s));
       }
   return FDLB_OK;
 }
@@ -653,5 +673,60 @@ extern "C" int fdlb_case_grid(const fdlb_params *p, double *x, double *jac) {
   if (build_case(*p, ch, why)) return fail(FDLB_EINVAL, why);
   if (x) memcpy(x, ch.x.data(), sizeof(double) * ch.nx);
   if (jac) memcpy(jac, ch.jac.data(), sizeof(double) * ch.nx);
+  return FDLB_OK;
+}
+
+// Average device time (ms) of each kernel of one step, measured with HIP
+// events on the caller's stream over nrep back-to-back launches of that kernel
+// alone (all active cases).  ms_out[7]: table pass (stage input f^n), update
+// stage 1, 2, 3 for the FP64 group, then update stage 1, 2, 3 for the FP32
+// group (0 where a group is empty).  The state is left as after one step.
+extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
+  if (!h || !ms_out || nrep <= 0) return fail(FDLB_EINVAL, "bad profile arguments");
+  for (int i = 0; i < 7; i++) ms_out[i] = 0;
+  hipEvent_t e0, e1;
+  HIPCHK(hipEventCreate(&e0));
+  HIPCHK(hipEventCreate(&e1));
+  auto timed = [&](auto &&launch, double *out) -> int {
+    int r = launch();
+    if (r) return r;
+    HIPCHK(hipEventRecord(e0, h->stream));
+    for (int k = 0; k < nrep; k++) { r = launch(); if (r) return r; }
+    HIPCHK(hipEventRecord(e1, h->stream));
+    HIPCHK(hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
+    *out = ms / nrep;
+    return FDLB_OK;
+  };
+  int r = FDLB_OK;
+  const int full = TM_PARTIALS | TM_TABLES | TM_WALLS | TM_WRITE_MOM;
+  double tab = 0;
+  for (int P = 0; P < 2 && !r; P++) {
+    if (h->nU[P] == 0) continue;
+    double t = 0;
+    r = timed([&]() -> int { HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], full, 0, h->stream)); return 0; }, &t);
+    tab += t;
+    for (int stage = 1; stage <= 3 && !r; stage++) {
+      if (stage > 1)  // tables of the new stage input
+        HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], full & ~TM_WRITE_MOM, stage - 1, h->stream));
+      r = timed([&]() -> int { HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[P], h->nU[P], h->waves, h->force[P], h->stream)); return 0; },
+                &ms_out[1 + 3 * P + (stage - 1)]);
+    }
+  }
+  ms_out[0] = tab;
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (r) return r;
+  for (auto &c : h->cases)
+    if (c.active) c.steps += 1;
+  HIPCHK(hipStreamSynchronize(h->stream));
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_copy_probe(const void *src, void *dst, size_t bytes, void *stream) {
+  if (!src || !dst || bytes % 32) return fail(FDLB_EINVAL, "copy probe needs 32-byte multiples");
+  HIPCHK(launch_copy_probe(src, dst, bytes, (hipStream_t)stream));
+  HIPCHK(hipStreamSynchronize((hipStream_t)stream));
   return FDLB_OK;
 }

@@ -11,7 +11,10 @@ constexpr int NB = 48;         // nodes of the half-range base rule used for pro
 constexpr int MAXQH = 32;      // largest half-range order per half
 constexpr int MAXQY = 8;       // largest full-range order on y and z
 constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
-constexpr int CTILE = 32;      // cells per table block
+#ifndef FDLB_CTILE
+#define FDLB_CTILE 16
+#endif
+constexpr int CTILE = FDLB_CTILE;  // cells per table block
 constexpr int CHALO = 6;       // moment halo of a table block
 constexpr int NRAW = 9;        // raw moment sums per cell
 

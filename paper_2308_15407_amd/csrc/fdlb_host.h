@@ -44,12 +44,13 @@ enum {
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
                         hipStream_t s);
 hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
-                         hipStream_t s);
+                         int force, hipStream_t s);
 hipError_t launch_fill(int prec, const CaseDev *cases, const int *map, int nblocks, int waves, int use_noise,
                        hipStream_t s);
 hipError_t launch_partials(int prec, const CaseDev *cases, const int *map, int nblocks, int waves,
                            hipStream_t s);
 hipError_t launch_zero_resid(const CaseDev *cases, int ncases, hipStream_t s);
 hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStream_t s);
+hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 
 }  // namespace fdlb

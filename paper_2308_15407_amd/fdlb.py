@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libfdlb.so")
+LIB_PATH = os.environ.get("FDLB_LIB", os.path.join(HERE, "libfdlb.so"))
 
 FDLB_OK, FDLB_EINVAL, FDLB_EHIP, FDLB_ENOMEM, FDLB_ENONFINITE, FDLB_ESTALL, FDLB_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FDLB_NMOM = 10
@@ -21,7 +21,8 @@ MOMENT_NAMES = ("n", "ux", "uy", "T", "qx", "qy", "Pxx", "Pxy", "Pyy", "Pzz")
 EXPORTS = ("fdlb_workspace_bytes", "fdlb_case_info", "fdlb_case_lattice", "fdlb_case_grid", "fdlb_init",
            "fdlb_step", "fdlb_moments", "fdlb_grid_coords", "fdlb_lattice", "fdlb_dt", "fdlb_run_to_steady",
            "fdlb_residual", "fdlb_set_state", "fdlb_get_f", "fdlb_set_f", "fdlb_case_precision",
-           "fdlb_set_tiling", "fdlb_set_graph_steps", "fdlb_destroy", "fdlb_last_error")
+           "fdlb_set_tiling", "fdlb_set_graph_steps", "fdlb_profile", "fdlb_copy_probe", "fdlb_destroy",
+           "fdlb_last_error")
 
 
 class FdlbError(RuntimeError):
@@ -88,6 +89,8 @@ def lib():
         L.fdlb_case_precision.argtypes = [P, I, C.POINTER(I)]
         L.fdlb_set_tiling.argtypes = [P, I, I]
         L.fdlb_set_graph_steps.argtypes = [P, I]
+        L.fdlb_profile.argtypes = [P, I, dp]
+        L.fdlb_copy_probe.argtypes = [P, P, Z, P]
         L.fdlb_destroy.argtypes = [P]
         L.fdlb_destroy.restype = None
         L.fdlb_last_error.restype = C.c_char_p
@@ -223,6 +226,16 @@ def fdlb_set_tiling(h, kx_per_chunk, waves):
 
 def fdlb_set_graph_steps(h, nsteps):
     _chk(lib().fdlb_set_graph_steps(h, int(nsteps)))
+
+
+def fdlb_profile(h, nrep):
+    out = np.zeros(7)
+    _chk(lib().fdlb_profile(h, int(nrep), _dptr(out)))
+    return out
+
+
+def fdlb_copy_probe(src_ptr, dst_ptr, nbytes, stream_ptr):
+    _chk(lib().fdlb_copy_probe(C.c_void_p(src_ptr), C.c_void_p(dst_ptr), int(nbytes), C.c_void_p(stream_ptr)))
 
 
 def fdlb_destroy(h):

@@ -87,6 +87,10 @@ class Solver:
     def set_graph_steps(self, n):
         F.fdlb_set_graph_steps(self.handle, n)
 
+    def profile(self, nrep=50):
+        """Per-kernel average ms: [table, update1..3 (FP64), update1..3 (FP32)]."""
+        return F.fdlb_profile(self.handle, nrep)
+
     def mass(self, c=0):
         x, jac = self.grid(c)
         return float(np.sum(self.moments(c)[0] * jac) * 2.0 / self.nx[c])

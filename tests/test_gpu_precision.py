@@ -1,0 +1,51 @@
+"""FP32-bulk storage with FP64 moments, wall balance and residual, against
+the FP64 oracle: per-moment errors (n, u, T, q, P_xy) are bounded at 1e-5
+(n, T pointwise relative; u, q, P_xy relative to their channel maximum)."""
+import numpy as np
+import pytest
+
+import fdlb_inputs as I
+from oracle import oracle as O
+from tests.gpu_util import rel_moment_errors, seeded_state
+
+pytestmark = pytest.mark.gpu
+
+TOL32 = 1e-5
+
+
+def _run_pair(cfg, steps, seed):
+    from paper_2308_15407_amd.solver import Solver
+    s = Solver(dict(cfg, precision=1))
+    o = O.Oracle(**cfg)
+    fields, noise = seeded_state(seed, cfg["nx"], o.K)
+    s.set_state(0, fields, noise)
+    o.set_state(fields, noise)
+    s.step(steps)
+    o.step(steps)
+    return s, o
+
+
+@pytest.mark.parametrize("name,over,steps", [("C1", {}, 200), ("C2", dict(nx=96, qx_half=6), 100),
+                                             ("C3", dict(nx=64, qx_half=6), 60)])
+def test_fp32_bulk_moment_errors(name, over, steps):
+    cfg = I.config(name, **over)
+    s, o = _run_pair(cfg, steps, 40)
+    err = rel_moment_errors(s.moments(0), o.moments())
+    print("FP32 bulk %s %d steps:" % (name, steps), {k: "%.1e" % v for k, v in err.items()}, flush=True)
+    for k in ("n", "ux", "uy", "T", "qx", "Pxy"):
+        assert err[k] < TOL32, (k, err[k])
+
+
+def test_fp32_run_to_steady_promotes_and_converges():
+    from paper_2308_15407_amd.solver import Solver
+    cfg = I.config("C1", nx=24)
+    o = O.Oracle(**cfg)
+    o.run_to_steady(1e-9, 200000)
+    s = Solver(dict(cfg, precision=1))
+    st, res, code = s.run_to_steady(tol=1e-8, max_steps=200000, check_every=50)
+    assert code == 0 and res[0] < 1e-8
+    assert s.precision(0) == 0          # finished on the FP64 tail after the FP32 stall
+    err = rel_moment_errors(s.moments(0), o.moments())
+    print("FP32->FP64 steady:", {k: "%.1e" % v for k, v in err.items()}, flush=True)
+    for k in ("n", "T"):
+        assert err[k] < 1e-7
