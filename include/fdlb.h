@@ -160,6 +160,36 @@ int fdlb_profile(fdlb_handle h, int nrep, double *ms_out);
    the given stream, used to calibrate hardware traffic counters. */
 int fdlb_copy_probe(const void *src, void *dst, size_t bytes, void *hip_stream);
 
+/* ------------------------------------------------------------------------
+   Warm-start network: a multilayer perceptron (n_in -> depth hidden layers of
+   `width` with GELU -> n_out), BF16 weights and activations with FP32
+   accumulation (MFMA), FP32 master weights, MSE loss and AdamW, trained and
+   evaluated by the library's own kernels.  Parameters are one flat FP32
+   vector: for each layer W[out][in] row-major, then b[out].  x, t, y are
+   device pointers to FP32 row-major [batch][n_in] / [batch][n_out].
+   ------------------------------------------------------------------------ */
+typedef struct fdlb_mlp_ctx *fdlb_mlp;
+size_t fdlb_mlp_workspace_bytes(int n_in, int width, int depth, int n_out, int max_batch);
+int fdlb_mlp_init(int n_in, int width, int depth, int n_out, int max_batch, void *dev_workspace, size_t bytes,
+                  void *hip_stream, fdlb_mlp *out);
+int fdlb_mlp_num_params(fdlb_mlp h, long *n);
+int fdlb_mlp_set_params(fdlb_mlp h, const float *host_params);   /* resets the optimiser state */
+int fdlb_mlp_get_params(fdlb_mlp h, float *host_params);
+int fdlb_mlp_forward(fdlb_mlp h, const float *x_dev, int batch, float *y_dev);
+/* forward + backward without an update: mean squared error and its gradient
+   with respect to every parameter (grad_host[num_params], may be NULL) */
+int fdlb_mlp_loss_grad(fdlb_mlp h, const float *x_dev, const float *t_dev, int batch, float *loss_host,
+                       float *grad_host);
+/* one AdamW step (beta 0.9 / 0.999, eps 1e-8, decoupled weight decay);
+   loss_host may be NULL to stay asynchronous */
+int fdlb_mlp_train_step(fdlb_mlp h, const float *x_dev, const float *t_dev, int batch, float lr,
+                        float weight_decay, float *loss_host);
+/* C[M][N] (ldc) = A * B for BF16 A(m,k) = A[m*sam + k*sak], B(k,n) = B[k*sbk + n*sbn] (synchronises) */
+int fdlb_mlp_gemm_bf16(const void *A, const void *B, float *C, int M, int N, int K, long sam, long sak, long sbk,
+                       long sbn, int ldc, void *hip_stream);
+void fdlb_mlp_destroy(fdlb_mlp h);
+const char *fdlb_mlp_last_error(void);
+
 /* Release host-side state (the caller still owns the workspace). */
 void fdlb_destroy(fdlb_handle h);
 

@@ -41,9 +41,10 @@ struct fdlb_ctx {
   unsigned long long *d_resid = nullptr;
   int *d_map = nullptr;       // map storage (int4 entries)
   size_t map_cap = 0;         // entries available
-  int *d_mapT[2] = {nullptr, nullptr}, *d_mapU[2] = {nullptr, nullptr};
-  int nT[2] = {0, 0}, nU[2] = {0, 0};
-  int force[2] = {0, 0};      // some case of the group has a body force
+  // launch groups: (storage precision, body force) -> 4 groups, so that a case
+  // always runs the same kernel instance whatever else is in the batch
+  int *d_mapT[4] = {nullptr, nullptr, nullptr, nullptr}, *d_mapU[4] = {nullptr, nullptr, nullptr, nullptr};
+  int nT[4] = {0, 0, 0, 0}, nU[4] = {0, 0, 0, 0};
   int waves = 4;
   int kx_user = 0;
   int graph_steps = 0;
@@ -174,8 +175,7 @@ static std::vector<int> xcd_interleave(const std::vector<int> &logical) {
 
 static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
-  std::vector<int> mt[2], mu[2];
-  h->force[0] = h->force[1] = 0;
+  std::vector<int> mt[4], mu[4];
   for (size_t ci = 0; ci < h->cases.size(); ci++) {
     CaseHost &c = h->cases[ci];
     CaseDev &d = h->hdev[ci];
@@ -185,8 +185,7 @@ static int build_maps(fdlb_ctx *h) {
     d.active = c.active ? 1 : 0;
     d.prec = c.prec;
     if (!c.active) continue;
-    const int P = c.prec;
-    if (c.p.ay != 0.0) h->force[P] = 1;
+    const int P = c.prec * 2 + (c.p.ay != 0.0 ? 1 : 0);
     const int nct = (c.nx + CTILE - 1) / CTILE, nut = (c.nx + UTILE - 1) / UTILE;
     for (int t = 0; t < nct; t++) { mt[P].insert(mt[P].end(), {(int)ci, t, 0, 0}); }
     mt[P].insert(mt[P].end(), {(int)ci, -1, 0, 0});
@@ -194,12 +193,12 @@ static int build_maps(fdlb_ctx *h) {
     for (int t = 0; t < nut; t++)
       for (int ch = 0; ch < c.nchunk; ch++) mu[P].insert(mu[P].end(), {(int)ci, t, ch, 0});
   }
-  for (int P = 0; P < 2; P++) mu[P] = xcd_interleave(mu[P]);
+  for (int P = 0; P < 4; P++) mu[P] = xcd_interleave(mu[P]);
   size_t need = 0;
-  for (int P = 0; P < 2; P++) need += (mt[P].size() + mu[P].size()) / 4;
+  for (int P = 0; P < 4; P++) need += (mt[P].size() + mu[P].size()) / 4;
   if (need > h->map_cap) return fail(FDLB_ENOMEM, "launch map exceeds its reserved space");
   size_t off = 0;
-  for (int P = 0; P < 2; P++) {
+  for (int P = 0; P < 4; P++) {
     h->d_mapT[P] = h->d_map + 4 * off;
     h->nT[P] = (int)(mt[P].size() / 4);
     if (!mt[P].empty())
@@ -223,19 +222,19 @@ static int build_maps(fdlb_ctx *h) {
 static int launch_steps(fdlb_ctx *h, long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++)
     for (int stage = 1; stage <= 3; stage++)
-      for (int P = 0; P < 2; P++) {
-        if (h->nU[P] == 0) continue;
+      for (int G = 0; G < 4; G++) {
+        if (h->nU[G] == 0) continue;
         int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
-        HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], mode, stage - 1, s));
-        HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[P], h->nU[P], h->waves, h->force[P], s));
+        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, s));
+        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, s));
       }
   return FDLB_OK;
 }
 
 static int launch_moments(fdlb_ctx *h, bool resid) {
   if (resid) HIPCHK(launch_zero_resid(h->d_cases, (int)h->cases.size(), h->stream));
-  for (int P = 0; P < 2; P++)
-    HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P],
+  for (int G = 0; G < 4; G++)
+    HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G],
                         TM_PARTIALS | TM_WRITE_MOM | (resid ? TM_RESID : 0), 0, h->stream));
   return FDLB_OK;
 }
@@ -580,11 +579,19 @@ extern "C" int fdlb_residual(fdlb_handle h, double *out) {
   return FDLB_OK;
 }
 
-static int promote_case(fdlb_ctx *h, int c) {
+static int promote_case(fdlb_ctx *h, int c, double mass0) {
   CaseHost &ch = h->cases[c];
   CaseDev &d = h->hdev[c];
   const size_t n = (size_t)ch.K * ch.nx;
+  // the FP32 phase conserves mass only to its rounding: restore the mass the
+  // case carried when the run started
+  std::vector<double> mom((size_t)FDLB_NMOM * ch.nx);
+  HIPCHK(hipMemcpyAsync(mom.data(), d.mom, sizeof(double) * mom.size(), hipMemcpyDeviceToHost, h->stream));
+  HIPCHK(hipStreamSynchronize(h->stream));
+  double mass = 0;
+  for (int i = 0; i < ch.nx; i++) mass += mom[i] * ch.jac[i] * ch.deta;
   HIPCHK(launch_convert(0, d.f[1][0], d.f[0][0], n, h->stream));
+  if (mass0 > 0 && mass > 0) HIPCHK(launch_scale(d.f[0][0], mass0 / mass, n, h->stream));
   ch.prec = 0;
   d.prec = 0;
   int r = upload_cases(h);
@@ -600,11 +607,21 @@ extern "C" int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, lon
   if (!(tol > 0) || max_steps < 0 || check_every <= 0) return fail(FDLB_EINVAL, "bad tol / max_steps / check_every");
   const int nc = (int)h->cases.size();
   std::vector<long> start(nc);
-  std::vector<double> best(nc, INFINITY);
+  std::vector<double> best(nc, INFINITY), mass0(nc, 0.0);
   std::vector<int> since_best(nc, 0);
   for (int i = 0; i < nc; i++) { start[i] = h->cases[i].steps; h->cases[i].active = true; }
   int r = build_maps(h);
   if (r) return r;
+  // mass of every case at the start (restored if an FP32 case is promoted)
+  r = launch_moments(h, false);
+  if (r) return r;
+  for (int i = 0; i < nc; i++) {
+    const CaseHost &ch = h->cases[i];
+    std::vector<double> n0(ch.nx);
+    HIPCHK(hipMemcpyAsync(n0.data(), h->hdev[i].mom, sizeof(double) * ch.nx, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int k = 0; k < ch.nx; k++) mass0[i] += n0[k] * ch.jac[k] * ch.deta;
+  }
   bool nonfinite = false;
   std::vector<double> res;
   for (;;) {
@@ -628,7 +645,7 @@ extern "C" int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, lon
       if (res[i] < tol || c.steps - start[i] >= max_steps) { c.active = false; changed = true; continue; }
       if (res[i] < 0.9 * best[i]) { best[i] = res[i]; since_best[i] = 0; }
       else if (++since_best[i] >= h->converge_hist && c.prec == 1) {
-        r = promote_case(h, i);
+        r = promote_case(h, i, mass0[i]);
         if (r) return r;
         best[i] = INFINITY; since_best[i] = 0;
       }
@@ -702,16 +719,18 @@ extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
   int r = FDLB_OK;
   const int full = TM_PARTIALS | TM_TABLES | TM_WALLS | TM_WRITE_MOM;
   double tab = 0;
-  for (int P = 0; P < 2 && !r; P++) {
-    if (h->nU[P] == 0) continue;
+  for (int G = 0; G < 4 && !r; G++) {
+    if (h->nU[G] == 0) continue;
+    const int P = G >> 1;
     double t = 0;
-    r = timed([&]() -> int { HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], full, 0, h->stream)); return 0; }, &t);
+    r = timed([&]() -> int { HIPCHK(launch_table(P, h->d_cases, h->d_mapT[G], h->nT[G], full, 0, h->stream)); return 0; }, &t);
     tab += t;
     for (int stage = 1; stage <= 3 && !r; stage++) {
       if (stage > 1)  // tables of the new stage input
-        HIPCHK(launch_table(P, h->d_cases, h->d_mapT[P], h->nT[P], full & ~TM_WRITE_MOM, stage - 1, h->stream));
-      r = timed([&]() -> int { HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[P], h->nU[P], h->waves, h->force[P], h->stream)); return 0; },
-                &ms_out[1 + 3 * P + (stage - 1)]);
+        HIPCHK(launch_table(P, h->d_cases, h->d_mapT[G], h->nT[G], full & ~TM_WRITE_MOM, stage - 1, h->stream));
+      double u = 0;
+      r = timed([&]() -> int { HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->stream)); return 0; }, &u);
+      ms_out[1 + 3 * P + (stage - 1)] += u;
     }
   }
   ms_out[0] = tab;

@@ -52,5 +52,6 @@ hipError_t launch_partials(int prec, const CaseDev *cases, const int *map, int n
 hipError_t launch_zero_resid(const CaseDev *cases, int ncases, hipStream_t s);
 hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
+hipError_t launch_scale(void *x, double a, size_t n, hipStream_t s);
 
 }  // namespace fdlb

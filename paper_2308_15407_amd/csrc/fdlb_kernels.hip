@@ -740,6 +740,10 @@ __global__ void k_zero_resid(const CaseDev *__restrict__ cases, int ncases) {
   if (i < ncases) *cases[i].resid = 0ull;
 }
 
+__global__ void k_scale(double *__restrict__ x, double a, size_t n) {
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] *= a;
+}
+
 template <typename S, typename D>
 __global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -814,6 +818,13 @@ hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStre
     hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks), dim3(256), 0, s, (const float *)src, (double *)dst, n);
   else
     hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks), dim3(256), 0, s, (const double *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_scale(void *x, double a, size_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  hipLaunchKernelGGL(k_scale, dim3(blocks), dim3(256), 0, s, (double *)x, a, n);
   return hipGetLastError();
 }
 

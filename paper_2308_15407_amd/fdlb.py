@@ -22,7 +22,9 @@ EXPORTS = ("fdlb_workspace_bytes", "fdlb_case_info", "fdlb_case_lattice", "fdlb_
            "fdlb_step", "fdlb_moments", "fdlb_grid_coords", "fdlb_lattice", "fdlb_dt", "fdlb_run_to_steady",
            "fdlb_residual", "fdlb_set_state", "fdlb_get_f", "fdlb_set_f", "fdlb_case_precision",
            "fdlb_set_tiling", "fdlb_set_graph_steps", "fdlb_profile", "fdlb_copy_probe", "fdlb_destroy",
-           "fdlb_last_error")
+           "fdlb_last_error", "fdlb_mlp_workspace_bytes", "fdlb_mlp_init", "fdlb_mlp_num_params",
+           "fdlb_mlp_set_params", "fdlb_mlp_get_params", "fdlb_mlp_forward", "fdlb_mlp_loss_grad",
+           "fdlb_mlp_train_step", "fdlb_mlp_gemm_bf16", "fdlb_mlp_destroy", "fdlb_mlp_last_error")
 
 
 class FdlbError(RuntimeError):
@@ -50,6 +52,7 @@ PARAM_DEFAULTS = dict(flow=0, kn=0.1, eta0=0.05, t_left=1.0, t_right=1.0, uy_lef
 
 def make_params(d):
     full = dict(PARAM_DEFAULTS)
+    d = {k: v for k, v in d.items() if not k.startswith("_")}   # caller bookkeeping keys
     unknown = set(d) - set(full)
     if unknown:
         raise TypeError("unknown case parameters: %s" % sorted(unknown))
@@ -64,6 +67,9 @@ def lib():
     """Load libfdlb.so (raises if it has not been built)."""
     global _lib
     if _lib is None:
+        # torch ships its own libamdhip64.so.7: load it first so that this
+        # library binds to the same HIP runtime as the tensors it is handed
+        import torch  # noqa: F401
         if not os.path.exists(LIB_PATH):
             raise ImportError("libfdlb.so is not built; run paper_2308_15407_amd.build.build()")
         L = C.CDLL(LIB_PATH)
@@ -94,8 +100,23 @@ def lib():
         L.fdlb_destroy.argtypes = [P]
         L.fdlb_destroy.restype = None
         L.fdlb_last_error.restype = C.c_char_p
+        fp = C.POINTER(C.c_float)
+        L.fdlb_mlp_workspace_bytes.restype = Z
+        L.fdlb_mlp_workspace_bytes.argtypes = [I, I, I, I, I]
+        L.fdlb_mlp_init.argtypes = [I, I, I, I, I, P, Z, P, C.POINTER(P)]
+        L.fdlb_mlp_num_params.argtypes = [P, C.POINTER(C.c_long)]
+        L.fdlb_mlp_set_params.argtypes = [P, fp]
+        L.fdlb_mlp_get_params.argtypes = [P, fp]
+        L.fdlb_mlp_forward.argtypes = [P, P, I, P]
+        L.fdlb_mlp_loss_grad.argtypes = [P, P, P, I, fp, fp]
+        L.fdlb_mlp_train_step.argtypes = [P, P, P, I, C.c_float, C.c_float, fp]
+        L.fdlb_mlp_gemm_bf16.argtypes = [P, P, P, I, I, I, C.c_long, C.c_long, C.c_long, C.c_long, I, P]
+        L.fdlb_mlp_destroy.argtypes = [P]
+        L.fdlb_mlp_destroy.restype = None
+        L.fdlb_mlp_last_error.restype = C.c_char_p
         for name in EXPORTS:
-            if name not in ("fdlb_workspace_bytes", "fdlb_destroy", "fdlb_last_error"):
+            if name not in ("fdlb_workspace_bytes", "fdlb_destroy", "fdlb_last_error", "fdlb_mlp_workspace_bytes",
+                            "fdlb_mlp_destroy", "fdlb_mlp_last_error"):
                 getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -240,3 +261,69 @@ def fdlb_copy_probe(src_ptr, dst_ptr, nbytes, stream_ptr):
 
 def fdlb_destroy(h):
     lib().fdlb_destroy(h)
+
+
+# --------------------------------------------------------------------------
+# warm-start network
+# --------------------------------------------------------------------------
+def _mchk(code):
+    if code != FDLB_OK:
+        raise FdlbError(code, lib().fdlb_mlp_last_error().decode())
+
+
+def _fptr(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float)) if a is not None else None
+
+
+def fdlb_mlp_workspace_bytes(n_in, width, depth, n_out, max_batch):
+    return lib().fdlb_mlp_workspace_bytes(n_in, width, depth, n_out, max_batch)
+
+
+def fdlb_mlp_init(n_in, width, depth, n_out, max_batch, ws_ptr, nbytes, stream_ptr):
+    h = C.c_void_p()
+    _mchk(lib().fdlb_mlp_init(n_in, width, depth, n_out, max_batch, C.c_void_p(ws_ptr), nbytes,
+                              C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def fdlb_mlp_num_params(h):
+    n = C.c_long()
+    _mchk(lib().fdlb_mlp_num_params(h, C.byref(n)))
+    return n.value
+
+
+def fdlb_mlp_set_params(h, params):
+    params = np.ascontiguousarray(params, dtype=np.float32)
+    _mchk(lib().fdlb_mlp_set_params(h, _fptr(params)))
+
+
+def fdlb_mlp_get_params(h, n):
+    out = np.zeros(n, dtype=np.float32)
+    _mchk(lib().fdlb_mlp_get_params(h, _fptr(out)))
+    return out
+
+
+def fdlb_mlp_forward(h, x_ptr, batch, y_ptr):
+    _mchk(lib().fdlb_mlp_forward(h, C.c_void_p(x_ptr), batch, C.c_void_p(y_ptr)))
+
+
+def fdlb_mlp_loss_grad(h, x_ptr, t_ptr, batch, nparams):
+    loss = np.zeros(1, dtype=np.float32)
+    grad = np.zeros(nparams, dtype=np.float32)
+    _mchk(lib().fdlb_mlp_loss_grad(h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), batch, _fptr(loss), _fptr(grad)))
+    return float(loss[0]), grad
+
+
+def fdlb_mlp_train_step(h, x_ptr, t_ptr, batch, lr, wd, want_loss=False):
+    loss = np.zeros(1, dtype=np.float32) if want_loss else None
+    _mchk(lib().fdlb_mlp_train_step(h, C.c_void_p(x_ptr), C.c_void_p(t_ptr), batch, lr, wd, _fptr(loss)))
+    return float(loss[0]) if want_loss else None
+
+
+def fdlb_mlp_gemm_bf16(a_ptr, b_ptr, c_ptr, M, N, K, sam, sak, sbk, sbn, ldc, stream_ptr):
+    _mchk(lib().fdlb_mlp_gemm_bf16(C.c_void_p(a_ptr), C.c_void_p(b_ptr), C.c_void_p(c_ptr), M, N, K, sam, sak, sbk,
+                                   sbn, ldc, C.c_void_p(stream_ptr)))
+
+
+def fdlb_mlp_destroy(h):
+    lib().fdlb_mlp_destroy(h)

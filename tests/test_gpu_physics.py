@@ -69,7 +69,7 @@ def test_uniform_maxwellian_invariant_and_mass_conserved():
 
 
 def test_batch_matches_single_bitwise():
-    cfgs = [I.config("C1", nx=40), I.config("C2", nx=70, qx_half=5), I.config("C3", nx=33, qx_half=3, qy=5, qz=3),
+    cfgs = [I.config("C1", nx=40), I.config("C2", nx=70, qx_half=5), I.config("C3", nx=33, qx_half=3, qy=5, qz=3, eta0=0.1),
             I.config("C2", nx=50, qx_half=4, precision=1)]
     b = _solver(cfgs)
     singles = [_solver(c) for c in cfgs]
