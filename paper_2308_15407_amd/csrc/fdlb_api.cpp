@@ -45,6 +45,7 @@ struct fdlb_ctx {
   // always runs the same kernel instance whatever else is in the batch
   int *d_mapT[4] = {nullptr, nullptr, nullptr, nullptr}, *d_mapU[4] = {nullptr, nullptr, nullptr, nullptr};
   int nT[4] = {0, 0, 0, 0}, nU[4] = {0, 0, 0, 0};
+  size_t lds[4] = {0, 0, 0, 0};   // dynamic LDS bytes of each group's update launch
   int waves = 4;
   int kx_user = 0;
   int graph_steps = 0;
@@ -176,6 +177,7 @@ static std::vector<int> xcd_interleave(const std::vector<int> &logical) {
 static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
   std::vector<int> mt[4], mu[4];
+  for (int G = 0; G < 4; G++) h->lds[G] = update_lds_bytes(G >> 1, 1, 1, h->waves, false);
   for (size_t ci = 0; ci < h->cases.size(); ci++) {
     CaseHost &c = h->cases[ci];
     CaseDev &d = h->hdev[ci];
@@ -184,8 +186,13 @@ static int build_maps(fdlb_ctx *h) {
     d.kxc = c.kxc; d.nchunk = c.nchunk;
     d.active = c.active ? 1 : 0;
     d.prec = c.prec;
+    const bool force = c.p.ay != 0.0;
+    const int qyz = c.qy * c.qz;
+    // update blocks of force-free cases stage their tables in LDS when they fit
+    d.tlds = (!force && update_lds_bytes(c.prec, qyz, c.kxc, h->waves, true) <= UPDATE_LDS_MAX) ? 1 : 0;
     if (!c.active) continue;
-    const int P = c.prec * 2 + (c.p.ay != 0.0 ? 1 : 0);
+    const int P = c.prec * 2 + (force ? 1 : 0);
+    h->lds[P] = std::max(h->lds[P], update_lds_bytes(c.prec, qyz, c.kxc, h->waves, d.tlds != 0));
     const int nct = (c.nx + CTILE - 1) / CTILE, nut = (c.nx + UTILE - 1) / UTILE;
     for (int t = 0; t < nct; t++) { mt[P].insert(mt[P].end(), {(int)ci, t, 0, 0}); }
     mt[P].insert(mt[P].end(), {(int)ci, -1, 0, 0});
@@ -226,7 +233,7 @@ static int launch_steps(fdlb_ctx *h, long nsteps, hipStream_t s) {
         if (h->nU[G] == 0) continue;
         int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
         HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, s));
-        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, s));
+        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
       }
   return FDLB_OK;
 }
@@ -729,7 +736,7 @@ extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
       if (stage > 1)  // tables of the new stage input
         HIPCHK(launch_table(P, h->d_cases, h->d_mapT[G], h->nT[G], full & ~TM_WRITE_MOM, stage - 1, h->stream));
       double u = 0;
-      r = timed([&]() -> int { HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->stream)); return 0; }, &u);
+      r = timed([&]() -> int { HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream)); return 0; }, &u);
       ms_out[1 + 3 * P + (stage - 1)] += u;
     }
   }

@@ -28,6 +28,8 @@ struct LatOff {
   int ck;           // 1/h_Q'(p_k) [qh]
   int Hy, Hz;       // w_k He_l(p_k)/l!  [qy*qy], [qz*qz]
   int fdw;          // one-sided 7-point first-derivative weights, rows for cells 0,1,2 [3*7]
+  int phi;          // moment weights of every velocity [K][8] (64-byte rows): px, py, px^2, px py,
+                    // py^2, pz^2, px |p|^2, py |p|^2 (the weight of the density sum is 1)
   int total;
 };
 
@@ -38,7 +40,7 @@ struct CaseDev {
   int prec;             // active storage: 0 double, 1 float
   int collision, j1_shear;
   int active;
-  int pad0;
+  int tlds;             // update blocks stage the projection tables of their tile in LDS
   double eta0, kn, chi0, pr_fixed, ay, dt;
   double tau_pre;       // (5 sqrt(2 pi)/16) Kn chi0 ; 0 when Kn = infinity
   double wallD[2];      // sum over emitted nodes of p_x g^w (left, right)

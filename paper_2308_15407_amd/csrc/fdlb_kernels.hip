@@ -27,6 +27,12 @@ namespace fdlb {
 // global address space lets the compiler emit global (not flat) memory
 // instructions with a uniform base and 32-bit lane offsets.
 #define GAS __attribute__((address_space(1)))
+// constant address space: read-only for the whole kernel, so uniform
+// addresses are read with scalar loads
+#define CAS __attribute__((address_space(4)))
+template <bool B>
+struct BoolC { static constexpr bool value = B; };
+
 template <typename T>
 __device__ __forceinline__ GAS T *gp(void *p) { return (GAS T *)p; }
 template <typename T>
@@ -40,6 +46,31 @@ __device__ __forceinline__ T ldb(const GAS T *row, unsigned bytes) {
 template <typename T>
 __device__ __forceinline__ void stb(GAS T *row, unsigned bytes, T v) {
   *(GAS T *)((GAS char *)row + bytes) = v;
+}
+// raw buffer access to one row of `bytes` bytes: the base stays in scalar
+// registers, lanes supply 32-bit byte offsets, and accesses outside the row
+// read zero / are dropped by the hardware range check
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const GAS void *row, unsigned bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  if constexpr (sizeof(T) == 8) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    const v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    return __builtin_bit_cast(T, v);
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+  }
+}
+template <typename T>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, T v) {
+  if constexpr (sizeof(T) == 8) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, (int)off, 0, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, 0, 0);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -74,12 +105,11 @@ __device__ __forceinline__ T weno_face(const T v0, const T v1, const T v2, const
   const T d3 = drop3 ? (T)0 : (T)0.3;
   if (drop3) b3 = (T)1;
   if (sizeof(T) == 4) {
+    // scale into [0, 1]; the tiny offset keeps bmax = 0 finite (all b stay 0)
     const T bmax = fmax(fmax(b1, b2), drop3 ? b2 : b3);
-    if (bmax > (T)0) {
-      const T r = fast_rcp(bmax);
-      b1 *= r; b2 *= r;
-      if (!drop3) b3 *= r;
-    }
+    const T r = fast_rcp(bmax + (T)1e-30f);
+    b1 *= r; b2 *= r;
+    if (!drop3) b3 *= r;
   }
   const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
   T w1 = (T)0.1 * p23 * p23, w2 = (T)0.6 * p13 * p13, w3 = d3 * p12 * p12;
@@ -421,20 +451,21 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
 // ---------------------------------------------------------------------------
 // update pass
 // ---------------------------------------------------------------------------
+// Sum the per-wave raw moment sums of a block into the chunk's partials.
+// s_acc: LDS of at least waves * NRAW * 64 doubles.
 template <typename T>
 __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int c0, double (&acc)[NRAW],
-                                               bool is_cell) {
-  __shared__ double s_acc[8][NRAW][64];
+                                               bool is_cell, double *s_acc) {
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
 #pragma unroll
-  for (int m = 0; m < NRAW; m++) s_acc[wv][m][lane] = acc[m];
+  for (int m = 0; m < NRAW; m++) s_acc[(wv * NRAW + m) * 64 + lane] = acc[m];
   __syncthreads();
   for (int it = threadIdx.x; it < NRAW * 64; it += blockDim.x) {
     const int m = it / 64, l = it % 64;
     const int cell = c0 + l;
     if (l < UTILE && cell < c.nx) {
       double s = 0;
-      for (int w = 0; w < nwv; w++) s += s_acc[w][m][l];
+      for (int w = 0; w < nwv; w++) s += s_acc[(w * NRAW + m) * 64 + l];
       gp<double>(c.part)[((size_t)chunk * NRAW + m) * c.nx + cell] = s;
     }
   }
@@ -453,6 +484,7 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 
 template <typename T, int STAGE, bool FORCE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_UPDATE_WPE, 8))) k_update(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
+  extern __shared__ double lds_dyn[];
   const int4 bm = map[blockIdx.x];
   if (bm.x < 0) return;
   const CaseDev &c = cases[bm.x];
@@ -550,76 +582,132 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
   };
 
   if (!FORCE) {
-    // rows (velocities) of the chunk split into contiguous ranges per wave;
-    // the loads of row r+1 are issued before the arithmetic of row r
+    // Rows (velocities) of the chunk are split into contiguous ranges per
+    // wave, positive-x rows first.  The row loop is unrolled by two with two
+    // register sets, so the loads of row r+1 are in flight while row r is
+    // computed without copies between the sets.
     const int nrows = (kx1 - kx0) * qyz;
     const int per = (nrows + nwv - 1) / nwv;
-    const int r0 = wv * per, r1 = min(r0 + per, nrows);
-    const size_t xa = (size_t)nkx * tstride, ya = (size_t)qyz * tstride;
-    struct Row { T t0, t1, t2, t3, t4, y0, y1, y2, y3, fnv, gw; };
-    auto load_row = [&](int r, Row &d) {
-      const int kx = kx0 + r / qyz, yz = r - (r / qyz) * qyz;
-      const int kap = kx * qyz + yz;
-      const bool pos = kx < c.qh;
-      const GAS T *row = gin + (size_t)kap * tstride;
-      if (pos) { d.t0 = ldb(row, op0); d.t1 = ldb(row, op1); d.t2 = ldb(row, op2); d.t3 = ldb(row, op3); d.t4 = ldb(row, op4); }
-      else { d.t0 = ldb(row, on0); d.t1 = ldb(row, on1); d.t2 = ldb(row, on2); d.t3 = ldb(row, on3); d.t4 = ldb(row, on4); }
-      const GAS T *t = tYZ + (size_t)yz * tstride;
-      d.y0 = ldb(t, bc); d.y1 = ldb(t + ya, bc); d.y2 = ldb(t + 2 * ya, bc); d.y3 = ldb(t + 3 * ya, bc);
-      if (STAGE != 1) d.fnv = ldb(fn + (size_t)kap * tstride, bc);
-      d.gw = (pos ? gwL : gwR)[kap];
-    };
-    Row cur, nxt;
-    if (r0 < r1) load_row(r0, cur);
-    int kx_cached = -1;
-    T X0 = 0, X1 = 0, X2 = 0, X3 = 0;
-    for (int r = r0; r < r1; r++) {
-      if (r + 1 < r1) load_row(r + 1, nxt);
-      const int kx = kx0 + r / qyz, yz = r - (r / qyz) * qyz;
-      const int kap = kx * qyz + yz;
-      if (kx != kx_cached) {
-        kx_cached = kx;
-        const GAS T *xr = tX + (size_t)kx * tstride;
-        X0 = ldb(xr, bc); X1 = ldb(xr + xa, bc); X2 = ldb(xr + 2 * xa, bc); X3 = ldb(xr + 3 * xa, bc);
+    const int r0 = min(wv * per, nrows), r1 = min(r0 + per, nrows);
+    const int rsplit = min(max((c.qh - kx0) * qyz, 0), nrows);
+    const int kap_base = kx0 * qyz;
+    const bool tlds = c.tlds != 0;
+    // LDS tables of the tile, four coefficients a = 0..3 adjacent per lane:
+    // sYZ[(yz * 64 + lane) * 4 + a], sX[(kl * 64 + lane) * 4 + a]
+    T *sYZ = (T *)lds_dyn, *sX = sYZ + 4 * qyz * 64;
+    if (tlds) {
+      const int jcl = min(c0 + lane, nx - 1);
+      for (int rr = wv; rr < 4 * qyz; rr += nwv) {
+        const int a = rr / qyz, yz = rr - a * qyz;
+        sYZ[(yz * 64 + lane) * 4 + a] = tYZ[((size_t)a * qyz + yz) * tstride + jcl];
       }
-      const double pxd = lat[c.lo.px + kx];
-      const bool pos = kx < c.qh;
-      const T fw = (T)((pos ? nwl : nwr) * (double)cur.gw);
-      T v0, v1, v2, cen, fh;
-      if (pos) {
-        v0 = gp0 ? fw : cur.t0; v1 = gp1 ? fw : cur.t1; v2 = gp2 ? fw : cur.t2;
-        cen = cur.t3;
-        const T w = weno_face<T>(v0, v1, v2, cur.t3, cur.t4, mode_p == 3 ? 0 : mode_p);
-        fh = (mode_p == 3) ? fw : w;
-      } else {
-        v0 = gn4 ? fw : cur.t0; v1 = gn3 ? fw : cur.t1; v2 = gn2 ? fw : cur.t2;
-        cen = v2;
-        const T w = weno_face<T>(v0, v1, v2, cur.t3, cur.t4, mode_n == 3 ? 0 : mode_n);
-        fh = (mode_n == 3) ? fw : w;
+      const int nk = kx1 - kx0;
+      for (int rr = wv; rr < 4 * nk; rr += nwv) {
+        const int a = rr / nk, k = rr - a * nk;
+        sX[(k * 64 + lane) * 4 + a] = tX[((size_t)a * nkx + kx0 + k) * tstride + jcl];
       }
-      const T fr = __shfl_down(fh, 1, 64);
-      const T F = X0 * cur.y0 + X1 * cur.y1 + X2 * cur.y2 + X3 * cur.y3;
-      const T L = -(T)pxd * dxi * (fr - fh) + (F - cen) * itau;
-      const T adv1 = cen + dt * L;
-      T o;
-      if (STAGE == 1) o = adv1;
-      else o = (STAGE == 2) ? (T)0.75 * cur.fnv + (T)0.25 * adv1 : cur.fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
-      if (is_cell) stb(out + (size_t)kap * tstride, bw, o);
-      const int ky = yz / qz, kz = yz - ky * qz;
-      const double pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
-      const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
-      const double od = is_cell ? (double)o : 0.0;
-      acc[0] += od;
-      acc[1] += pxd * od;
-      acc[2] += pyd * od;
-      acc[3] += (pxd * pxd) * od;
-      acc[4] += (pxd * pyd) * od;
-      acc[5] += (pyd * pyd) * od;
-      acc[6] += (pzd * pzd) * od;
-      acc[7] += (pxd * p2) * od;
-      acc[8] += (pyd * p2) * od;
-      cur = nxt;
+      __syncthreads();
     }
+    const bool interior = tlds && c0 >= 3 && c0 + 66 <= nx;
+    const CAS double *__restrict__ phi = (const CAS double *)(c.lat + c.lo.phi);
+    typedef T T4 __attribute__((ext_vector_type(4)));
+    const unsigned rowbytes = (unsigned)nx * (unsigned)sizeof(T);
+    // global loads of a row (stencil of the stage input and f^n) are issued
+    // two rows ahead; the tables (LDS, short latency) are read at the start of
+    // the row's arithmetic
+    struct Row { T t0, t1, t2, t3, t4, fnv; };
+    // POS: upwind from the left (p_x > 0); WALL: ghost cells and boundary
+    // faces may occur in the tile; TL: tables from LDS
+    auto rows = [&](auto posc, auto wallc, auto tlc, int ra, int rb) {
+      constexpr bool POS = decltype(posc)::value, WALL = decltype(wallc)::value, TL = decltype(tlc)::value;
+      if (ra >= rb) return;
+      const unsigned o0 = POS ? op0 : on0, o1 = POS ? op1 : on1, o2 = POS ? op2 : on2, o3 = POS ? op3 : on3,
+                     o4 = POS ? op4 : on4;
+      const bool g0 = POS ? gp0 : gn4, g1 = POS ? gp1 : gn3, g2 = POS ? gp2 : gn2;
+      const int mode = POS ? mode_p : mode_n;
+      auto load = [&](int r, Row &d) {
+        const int kap = kap_base + r;
+        const auto rs = rsrc_of(gin + (size_t)kap * tstride, rowbytes);
+        d.t0 = bld<T>(rs, o0); d.t1 = bld<T>(rs, o1); d.t2 = bld<T>(rs, o2); d.t3 = bld<T>(rs, o3);
+        d.t4 = bld<T>(rs, o4);
+        if (STAGE != 1) d.fnv = bld<T>(rsrc_of(fn + (size_t)kap * tstride, rowbytes), bc);
+      };
+      auto compute = [&](int r, const Row &d) {
+        const int kap = kap_base + r;
+        const int kl = r / qyz, yz = r - kl * qyz;
+        const int kx = kx0 + kl;
+        const CAS double *ph = phi + (size_t)kap * 8;
+        const double pxd = ph[0];
+        T y0, y1, y2, y3, x0, x1, x2, x3;
+        if (TL) {
+          const T4 yv = *(const T4 *)(sYZ + (yz * 64 + lane) * 4);
+          const T4 xv = *(const T4 *)(sX + (kl * 64 + lane) * 4);
+          y0 = yv.x; y1 = yv.y; y2 = yv.z; y3 = yv.w;
+          x0 = xv.x; x1 = xv.y; x2 = xv.z; x3 = xv.w;
+        } else {
+          const size_t ya = (size_t)qyz * tstride, xa = (size_t)nkx * tstride;
+          const GAS T *y = tYZ + (size_t)yz * tstride, *x = tX + (size_t)kx * tstride;
+          y0 = ldb(y, bc); y1 = ldb(y + ya, bc); y2 = ldb(y + 2 * ya, bc); y3 = ldb(y + 3 * ya, bc);
+          x0 = ldb(x, bc); x1 = ldb(x + xa, bc); x2 = ldb(x + 2 * xa, bc); x3 = ldb(x + 3 * xa, bc);
+        }
+        T v0 = d.t0, v1 = d.t1, v2 = d.t2, cen;
+        T fh;
+        if (WALL) {
+          const T fw = (T)((POS ? nwl : nwr) * (double)(POS ? gwL : gwR)[kap]);
+          if (g0) v0 = fw;
+          if (g1) v1 = fw;
+          if (g2) v2 = fw;
+          cen = POS ? d.t3 : v2;
+          const T w = weno_face<T>(v0, v1, v2, d.t3, d.t4, mode == 3 ? 0 : mode);
+          fh = (mode == 3) ? fw : w;
+        } else {
+          cen = POS ? d.t3 : v2;
+          fh = weno_face<T>(v0, v1, v2, d.t3, d.t4, 0);
+        }
+        const T fr = __shfl_down(fh, 1, 64);
+        const T F = x0 * y0 + x1 * y1 + x2 * y2 + x3 * y3;
+        const T L = (-(T)pxd * dxi) * (fr - fh) + (F - cen) * itau;
+        const T adv1 = cen + dt * L;
+        T o;
+        if (STAGE == 1) o = adv1;
+        else o = (STAGE == 2) ? (T)0.75 * d.fnv + (T)0.25 * adv1 : d.fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
+        if (is_cell) bst<T>(rsrc_of(out + (size_t)kap * tstride, rowbytes), bw, o);
+        // lanes that own no cell accumulate values that are never stored
+        const double od = (double)o;
+        acc[0] += od;
+#pragma unroll
+        for (int m = 1; m < NRAW; m++) acc[m] = __builtin_fma(ph[m - 1], od, acc[m]);
+      };
+      // three register sets rotate: rows r+1 and r+2 are in flight while row
+      // r is computed
+      Row A, B, C;
+      load(ra, A);
+      if (ra + 1 < rb) load(ra + 1, B);
+      int r = ra;
+      for (; r + 2 < rb; r += 3) {
+        load(r + 2, C);
+        compute(r, A);
+        if (r + 3 < rb) load(r + 3, A);
+        compute(r + 1, B);
+        if (r + 4 < rb) load(r + 4, B);
+        compute(r + 2, C);
+      }
+      if (r < rb) compute(r, A);
+      if (r + 1 < rb) compute(r + 1, B);
+    };
+    using TT = BoolC<true>;
+    using FF = BoolC<false>;
+    if (interior) {
+      rows(TT(), FF(), TT(), r0, min(r1, rsplit));
+      rows(FF(), FF(), TT(), max(r0, rsplit), r1);
+    } else if (tlds) {
+      rows(TT(), TT(), TT(), r0, min(r1, rsplit));
+      rows(FF(), TT(), TT(), max(r0, rsplit), r1);
+    } else {
+      rows(TT(), TT(), FF(), r0, min(r1, rsplit));
+      rows(FF(), TT(), FF(), max(r0, rsplit), r1);
+    }
+    if (tlds) __syncthreads();   // the tables' LDS is reused by the partial sums
   } else {
     // body force couples the velocities of one y-line: a wave takes whole lines
     const T ay = (T)c.ay;
@@ -660,7 +748,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       }
     }
   }
-  block_partials<T>(c, bm.z, c0, acc, is_cell);
+  block_partials<T>(c, bm.z, c0, acc, is_cell, lds_dyn);
 }
 
 // initial state from the tables: f = sum_a n X_a YZ_a (times 1 + noise)
@@ -700,7 +788,10 @@ __global__ void __launch_bounds__(512) k_fill(const CaseDev *__restrict__ cases,
       acc[5] += pyd * pyd * od; acc[6] += pzd * pzd * od; acc[7] += pxd * p2 * od; acc[8] += pyd * p2 * od;
     }
   }
-  block_partials<T>(c, bm.z, c0, acc, is_cell);
+  {
+    __shared__ double s_acc[8 * NRAW * 64];
+    block_partials<T>(c, bm.z, c0, acc, is_cell, s_acc);
+  }
 }
 
 // partial raw sums of f^n (after an upload)
@@ -732,7 +823,10 @@ __global__ void __launch_bounds__(512) k_partials(const CaseDev *__restrict__ ca
       acc[5] += pyd * pyd * od; acc[6] += pzd * pzd * od; acc[7] += pxd * p2 * od; acc[8] += pyd * p2 * od;
     }
   }
-  block_partials<T>(c, bm.z, c0, acc, is_cell);
+  {
+    __shared__ double s_acc[8 * NRAW * 64];
+    block_partials<T>(c, bm.z, c0, acc, is_cell, s_acc);
+  }
 }
 
 __global__ void k_zero_resid(const CaseDev *__restrict__ cases, int ncases) {
@@ -770,19 +864,26 @@ hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblo
 }
 
 template <typename T, bool FORCE>
-static void upd(int stage, dim3 g, dim3 b, hipStream_t s, const CaseDev *cases, const int4 *map) {
-  if (stage == 1) hipLaunchKernelGGL((k_update<T, 1, FORCE>), g, b, 0, s, cases, map);
-  else if (stage == 2) hipLaunchKernelGGL((k_update<T, 2, FORCE>), g, b, 0, s, cases, map);
-  else hipLaunchKernelGGL((k_update<T, 3, FORCE>), g, b, 0, s, cases, map);
+static void upd(int stage, dim3 g, dim3 b, size_t lds, hipStream_t s, const CaseDev *cases, const int4 *map) {
+  if (stage == 1) hipLaunchKernelGGL((k_update<T, 1, FORCE>), g, b, lds, s, cases, map);
+  else if (stage == 2) hipLaunchKernelGGL((k_update<T, 2, FORCE>), g, b, lds, s, cases, map);
+  else hipLaunchKernelGGL((k_update<T, 3, FORCE>), g, b, lds, s, cases, map);
+}
+
+size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds) {
+  const size_t part = (size_t)waves * NRAW * 64 * sizeof(double);
+  const size_t tab = tlds ? (size_t)4 * (qyz + kxc) * 64 * (prec == 0 ? 8 : 4) : 0;
+  return part > tab ? part : tab;
 }
 
 hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
-                         int force, hipStream_t s) {
+                         int force, size_t lds, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
+  if (lds > UPDATE_LDS_MAX || lds < (size_t)waves * NRAW * 64 * sizeof(double)) return hipErrorInvalidValue;
   const dim3 g(nblocks), b(64 * waves);
   const int4 *m = (const int4 *)map;
-  if (prec == 0) { if (force) upd<double, true>(stage, g, b, s, cases, m); else upd<double, false>(stage, g, b, s, cases, m); }
-  else { if (force) upd<float, true>(stage, g, b, s, cases, m); else upd<float, false>(stage, g, b, s, cases, m); }
+  if (prec == 0) { if (force) upd<double, true>(stage, g, b, lds, s, cases, m); else upd<double, false>(stage, g, b, lds, s, cases, m); }
+  else { if (force) upd<float, true>(stage, g, b, lds, s, cases, m); else upd<float, false>(stage, g, b, lds, s, cases, m); }
   return hipGetLastError();
 }
 

@@ -203,6 +203,8 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   o.Hy = off; off += c.qy * c.qy;
   o.Hz = off; off += c.qz * c.qz;
   o.fdw = off; off += 3 * 7;
+  off = (off + 7) & ~7;   // 64-byte aligned rows (one scalar load per velocity)
+  o.phi = off; off += c.K * 8;
   o.total = off;
   c.lat.assign(off, 0.0);
   double *L = c.lat.data();
@@ -281,6 +283,17 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     lagrange_d1((ld)r, xs, 7, w7);
     for (int j = 0; j < 7; j++) L[o.fdw + r * 7 + j] = (double)w7[j];
   }
+  // moment weights per velocity
+  for (int kx = 0; kx < 2 * Q; kx++)
+    for (int ky = 0; ky < c.qy; ky++)
+      for (int kz = 0; kz < c.qz; kz++) {
+        const int kap = (kx * c.qy + ky) * c.qz + kz;
+        const double px = L[o.px + kx], py = L[o.py + ky], pz = L[o.pz + kz];
+        const double p2 = px * px + py * py + pz * pz;
+        double *ph = &L[o.phi + kap * 8];
+        ph[0] = px; ph[1] = py; ph[2] = px * px; ph[3] = px * py; ph[4] = py * py; ph[5] = pz * pz;
+        ph[6] = px * p2; ph[7] = py * p2;
+      }
   // grid: eta_i = -1 + (i + 1/2) deta; x = (L_c/2) eta or (L_c/2) tanh(d eta)/tanh(d)
   c.deta = 2.0 / c.nx;
   c.x.assign(c.nx, 0); c.jac.assign(c.nx, 0); c.invdx.assign(c.nx, 0);

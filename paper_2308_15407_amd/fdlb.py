@@ -208,7 +208,7 @@ def fdlb_run_to_steady(h, ncases, tol, max_steps, check_every):
     steps = (C.c_long * ncases)()
     res = np.zeros(ncases)
     code = _chk(lib().fdlb_run_to_steady(h, tol, int(max_steps), int(check_every), steps, _dptr(res)),
-                allow=(FDLB_ESTALL,))
+                allow=(FDLB_ESTALL, FDLB_ENONFINITE))
     return np.array(list(steps)), res, code
 
 

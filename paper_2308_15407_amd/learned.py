@@ -1,0 +1,288 @@
+"""Learned warm start for steady channel flows.
+
+A multilayer perceptron (library kernels, see mlp.py) maps the problem
+statement of a case -- flow type, Kn, eta0, wall temperatures and velocities,
+body force -- to the steady profiles of n, u_y, T, q_x and P_xy at 128
+Chebyshev points across the channel.  The prediction is interpolated to the
+case grid (barycentric formula), n is rescaled to the case's exact mass, and
+the state is set as the Grad-13-type distribution of the C ABI
+(fdlb_set_state).  A case falls back to the uniform cold start if the
+prediction is non-physical (n <= 0 or T <= 0) or the warm-started run fails.
+
+Training data are steady states the solver itself computes for cases drawn
+from the sweep generator.
+"""
+import json
+import math
+import os
+import time
+
+import numpy as np
+
+from . import fdlb as F
+
+NCHEB = 128
+FIELDS = ("n", "uy", "T", "qx", "Pxy")
+MOM_INDEX = {"n": 0, "ux": 1, "uy": 2, "T": 3, "qx": 4, "qy": 5, "Pxx": 6, "Pxy": 7, "Pyy": 8, "Pzz": 9}
+N_IN = 10
+N_OUT = NCHEB * len(FIELDS)
+
+
+def features(case):
+    """[onehot(flow) x3, log10 Kn, eta0, T_L, T_R, U_L, U_R, a_y]"""
+    oh = [0.0, 0.0, 0.0]
+    oh[int(case["flow"])] = 1.0
+    return np.array(oh + [math.log10(case["kn"]), case["eta0"], case["t_left"], case["t_right"],
+                          case["uy_left"], case["uy_right"], case["ay"]], dtype=np.float64)
+
+
+def cheb_points(Lc, n=NCHEB):
+    """Chebyshev points of the first kind on [-Lc/2, Lc/2] (decreasing order)."""
+    j = np.arange(n)
+    return 0.5 * Lc * np.cos(np.pi * (2 * j + 1) / (2 * n))
+
+
+def cheb_weights(n=NCHEB):
+    j = np.arange(n)
+    return (-1.0) ** j * np.sin(np.pi * (2 * j + 1) / (2 * n))
+
+
+def barycentric(xc, vals, x, w=None):
+    """Interpolate values at Chebyshev points xc to points x (barycentric form)."""
+    w = cheb_weights(len(xc)) if w is None else w
+    d = x[:, None] - xc[None, :]
+    exact = np.isclose(d, 0.0, atol=1e-15)
+    d = np.where(exact, 1.0, d)
+    t = w[None, :] / d
+    out = (t @ vals.T).T / t.sum(axis=1)
+    hit = exact.any(axis=1)
+    if hit.any():
+        out[..., hit] = vals[..., exact[hit].argmax(axis=1)]
+    return out
+
+
+def grid_to_points(xg, vals, x):
+    """Local cubic Lagrange interpolation from cell centres to points x
+    (extrapolating by at most half a cell next to the walls)."""
+    nx = len(xg)
+    out = np.empty((vals.shape[0], len(x)))
+    for k, xx in enumerate(x):
+        i = int(np.clip(np.searchsorted(xg, xx) - 2, 0, nx - 4))
+        xs = xg[i:i + 4]
+        L = np.ones(4)
+        for a in range(4):
+            for b in range(4):
+                if a != b:
+                    L[a] *= (xx - xs[b]) / (xs[a] - xs[b])
+        out[:, k] = vals[:, i:i + 4] @ L
+    return out
+
+
+def targets_from_moments(mom, xg, Lc):
+    """Steady moments [10][nx] -> flat target vector (field-major, 5 x 128)."""
+    v = np.stack([mom[MOM_INDEX[f]] for f in FIELDS])
+    return grid_to_points(xg, v, cheb_points(Lc)).ravel()
+
+
+class Standardizer:
+    """Per-field mean and standard deviation of the targets."""
+
+    def __init__(self, mean=None, std=None):
+        self.mean, self.std = mean, std
+
+    def fit(self, Y):
+        Yf = Y.reshape(len(Y), len(FIELDS), NCHEB)
+        self.mean = Yf.mean(axis=(0, 2))
+        self.std = Yf.std(axis=(0, 2)) + 1e-12
+        return self
+
+    def encode(self, Y):
+        Yf = Y.reshape(len(Y), len(FIELDS), NCHEB)
+        return ((Yf - self.mean[None, :, None]) / self.std[None, :, None]).reshape(len(Y), -1)
+
+    def decode(self, Z):
+        Zf = Z.reshape(len(Z), len(FIELDS), NCHEB)
+        return (Zf * self.std[None, :, None] + self.mean[None, :, None]).reshape(len(Z), -1)
+
+
+class FeatureScaler:
+    def __init__(self, mean=None, std=None):
+        self.mean, self.std = mean, std
+
+    def fit(self, X):
+        self.mean, self.std = X.mean(axis=0), X.std(axis=0) + 1e-9
+        return self
+
+    def __call__(self, X):
+        return (X - self.mean) / self.std
+
+
+# --------------------------------------------------------------------------
+# cases and data
+# --------------------------------------------------------------------------
+def study_params(draw, nx=64, qx_max=8):
+    """Case of the learned-warm-start study from one sweep draw: the draw's
+    flow, Kn, eta0 and wall/force data on an nx-cell uniform grid with the
+    draw's half-range order capped at qx_max, Q_y = Q_z = 4."""
+    import fdlb_inputs as I
+    d = I.c4_params(draw)
+    d.update(nx=nx, grid=0, stretch=0.0, qx_half=min(draw["qx_half"], qx_max))
+    return d
+
+
+def accept(case, r_min=2.0, kn_min=0.05):
+    """Keep draws with confinement ratio R >= r_min and Kn >= kn_min."""
+    try:
+        info = F.fdlb_case_info(case)
+    except F.FdlbError:
+        return False
+    return info["R"] >= r_min and case["kn"] >= kn_min
+
+
+def draw_cases(seed0, n, r_min=2.0, kn_min=0.05, nx=64, qx_max=8):
+    import fdlb_inputs as I
+    out, seed = [], seed0
+    while len(out) < n:
+        d = I.c4_draws(seed, 1)[0]
+        c = study_params(d, nx=nx, qx_max=qx_max)
+        if accept(c, r_min, kn_min):
+            c["_seed"] = seed
+            out.append(c)
+        seed += 1
+    return out
+
+
+def solve_steady(cases, tol, max_steps, check_every=200, precision=1, fields=None, log=None):
+    """Batched solve of `cases` (all in one launch map) to the residual tol.
+    Returns (moments list, grids, steps, residuals, wall seconds); a case that
+    diverged has a non-finite residual (the others still run to the end)."""
+    import torch
+    from .solver import Solver
+    cs = [dict({k: v for k, v in c.items() if not k.startswith("_")}, precision=precision) for c in cases]
+    t0 = time.perf_counter()
+    s = Solver(cs)
+    if fields is not None:
+        for i, f in enumerate(fields):
+            if f is not None:
+                s.set_state(i, f)
+    st, res, code = s.run_to_steady(tol=tol, max_steps=max_steps, check_every=check_every)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    moms = [s.moments(i) for i in range(len(cs))]
+    grids = [s.grid(i)[0] for i in range(len(cs))]
+    s.close()
+    return moms, grids, st, res, wall
+
+
+def solve_steady_warm(cases, fields, tol, max_steps, check_every=200, precision=1):
+    """Warm-started batched solve with the plain solve as fallback: cases
+    without a physical prediction start cold, and cases whose warm-started run
+    diverges or misses tol are solved again from the cold start.  Returns
+    (moments, grids, steps, residuals, wall seconds, number of fallbacks);
+    wall time and steps include the failed warm attempts."""
+    moms, grids, st, res, wall = solve_steady(cases, tol, max_steps, check_every, precision, fields)
+    bad = [i for i in range(len(cases)) if not (res[i] < tol)]
+    if bad:
+        m2, g2, s2, r2, w2 = solve_steady([cases[i] for i in bad], tol, max_steps, check_every, precision)
+        wall += w2
+        st = st.copy()
+        res = res.copy()
+        for k, i in enumerate(bad):
+            moms[i], grids[i], res[i] = m2[k], g2[k], r2[k]
+            st[i] += s2[k]
+    return moms, grids, st, res, wall, len(bad)
+
+
+def build_dataset(cases, tol=1e-6, max_steps=400000, batch=256, log=print):
+    X, Y, keep = [], [], []
+    for b0 in range(0, len(cases), batch):
+        chunk = cases[b0:b0 + batch]
+        moms, grids, st, res, wall = solve_steady(chunk, tol, max_steps)
+        if log:
+            log("  data batch %d-%d: %.1f s, steps max %d, residual max %.2e" % (b0, b0 + len(chunk), wall, st.max(),
+                                                                                 np.max(res)))
+        for c, m, xg, r in zip(chunk, moms, grids, res):
+            if not (r < 100 * tol) or not np.all(np.isfinite(m)):
+                continue
+            info = F.fdlb_case_info(c)
+            X.append(features(c))
+            Y.append(targets_from_moments(m, xg, info["Lc"]))
+            keep.append(c)
+    return np.array(X), np.array(Y), keep
+
+
+# --------------------------------------------------------------------------
+# model
+# --------------------------------------------------------------------------
+class WarmStartModel:
+    def __init__(self, net=None, fscale=None, tscale=None):
+        self.net, self.fscale, self.tscale = net, fscale, tscale
+
+    def fit(self, X, Y, epochs=600, batch=256, lr=1e-3, wd=1e-5, seed=0, log=print):
+        import torch
+        from .mlp import WarmStartNet
+        self.fscale = FeatureScaler().fit(X)
+        self.tscale = Standardizer().fit(Y)
+        Xs = self.fscale(X).astype(np.float32)
+        Ys = self.tscale.encode(Y).astype(np.float32)
+        if self.net is None:
+            self.net = WarmStartNet(N_IN, 256, 4, N_OUT, max_batch=max(batch, 512), seed=seed)
+        dX = torch.from_numpy(Xs).cuda()
+        dY = torch.from_numpy(Ys).cuda()
+        rng = np.random.default_rng(seed)
+        n = len(Xs)
+        nb = max(1, n // batch)
+        t0 = time.perf_counter()
+        hist = []
+        for ep in range(epochs):
+            perm = torch.from_numpy(rng.permutation(n)).cuda()
+            lr_ep = lr * 0.5 * (1 + math.cos(math.pi * ep / epochs))
+            for b in range(nb):
+                idx = perm[b * batch:(b + 1) * batch]
+                last = (b == nb - 1) and (ep % 50 == 0 or ep == epochs - 1)
+                L = self.net.train_step(dX[idx].contiguous(), dY[idx].contiguous(), lr_ep, wd, want_loss=last)
+                if last:
+                    hist.append((ep, L))
+                    if log:
+                        log("  epoch %d loss %.4e" % (ep, L))
+        torch.cuda.synchronize()
+        self.train_seconds = time.perf_counter() - t0
+        self.history = hist
+        return self
+
+    def predict(self, cases):
+        X = self.fscale(np.array([features(c) for c in cases])).astype(np.float32)
+        Z = self.net.forward(X).cpu().numpy().astype(np.float64)
+        return self.tscale.decode(Z)
+
+    def save(self, path):
+        np.savez(path, params=self.net.get_params(), fmean=self.fscale.mean, fstd=self.fscale.std,
+                 tmean=self.tscale.mean, tstd=self.tscale.std)
+
+    @classmethod
+    def load(cls, path, seed=0):
+        from .mlp import WarmStartNet
+        z = np.load(path)
+        net = WarmStartNet(N_IN, 256, 4, N_OUT, max_batch=512, seed=seed)
+        net.set_params(z["params"].astype(np.float32))
+        return cls(net, FeatureScaler(z["fmean"], z["fstd"]), Standardizer(z["tmean"], z["tstd"]))
+
+
+def warm_fields(case, pred):
+    """Prediction (5 x 128 at Chebyshev points) -> fields [6][nx] for
+    fdlb_set_state, or None if non-physical.  n is rescaled to the case mass
+    (uniform initial density n_init over L_c)."""
+    info = F.fdlb_case_info(case)
+    xg, jac = F.fdlb_case_grid(case)
+    v = barycentric(cheb_points(info["Lc"]), pred.reshape(len(FIELDS), NCHEB), xg)
+    n, uy, T, qx, pxy = v
+    if not (np.all(n > 0) and np.all(T > 0) and np.all(np.isfinite(v))):
+        return None
+    deta = 2.0 / case["nx"]
+    mass0 = case["n_init"] * np.sum(jac) * deta          # mass of the uniform cold start
+    n = n * mass0 / np.sum(n * jac * deta)
+    return np.stack([n, np.zeros_like(n), uy, T, qx, pxy])
+
+
+def default_weights_path():
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_weights.npz")

@@ -101,9 +101,9 @@ def test_nonfinite_state_is_reported():
     f = s.get_f(0)
     f[5, 7] = np.nan
     s.set_f(0, f)
-    with pytest.raises(F.FdlbError) as e:
-        s.run_to_steady(tol=1e-8, max_steps=1000, check_every=10)
-    assert e.value.code == F.FDLB_ENONFINITE
+    # the case is retired at its first check; the call reports it and still fills the outputs
+    st, res, code = s.run_to_steady(tol=1e-8, max_steps=1000, check_every=10)
+    assert code == F.FDLB_ENONFINITE and not np.isfinite(res[0]) and st[0] == 10
 
 
 def test_stall_reports_estall():
