@@ -34,6 +34,9 @@ def parse():
     ap.add_argument("--no-extra", action="store_true", help="only the main workload")
     ap.add_argument("--large-steps", type=int, default=60)
     ap.add_argument("--retune", action="store_true")
+    ap.add_argument("--sweep-steps", type=int, default=100)
+    ap.add_argument("--tts-batch", type=int, default=64, help="held-out cases in the learned time-to-steady leg")
+    ap.add_argument("--tts-seq", type=int, default=8, help="cases solved one at a time by the plain FP64 leg")
     return ap.parse_args()
 
 
@@ -79,7 +82,8 @@ def measure(cfg, steps, warmup, retune, graph_steps=50):
     tile = autotune.tune(s, use_cache=not retune)
     s.set_graph_steps(graph_steps)
     ms = timed_run(s, steps, warmup)
-    nodes = cfg["nx"] * 2 * cfg["qx_half"] * cfg["qy"] * cfg["qz"]
+    cases = cfg if isinstance(cfg, list) else [cfg]
+    nodes = sum(c["nx"] * 2 * c["qx_half"] * c["qy"] * c["qz"] for c in cases)
     prof = s.profile(nrep=20)
     return s, ms, nodes, tile, prof
 
@@ -109,6 +113,56 @@ def cpu_baseline(cfg, budget_s=15.0):
     nodes = cfg["nx"] * o.K
     return {"value": nodes * n / dt, "unit": "node-velocity updates/s", "cores": 1, "kind": "oracle",
             "sample": "%d RK3 steps of the same case (Nx=%d, K=%d) on one host thread, %.1f s" % (n, cfg["nx"], o.K, dt)}
+
+
+def sweep_leg(steps, retune):
+    """All cases of the seeded sweep (256 cases, FP32 bulk) advance together in
+    one launch map per stage, replayed from a HIP graph."""
+    from paper_2308_15407_amd import sweep
+    cases = sweep.sweep_cases(256)
+    s, ms, _, tile, prof = measure(cases, steps, 10, retune, graph_steps=20)
+    nodes = sum(c["nx"] * 2 * c["qx_half"] * c["qy"] * c["qz"] for c in cases)
+    return {"workload": "sweep: 256 seeded cases (PCG64 %d, R >= 2), Nx 64-512, Q_x^h 4-16 x 4 x 4, FP32 bulk"
+                        % sweep.SWEEP_SEED,
+            "value": round(nodes / (ms * 1e-3), 1), "unit": "node-velocity updates/s", "ms_per_step": round(ms, 5),
+            "nodes": nodes, "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}}
+
+
+def time_to_steady_leg(n_batch, n_seq, tol=1e-8, max_steps=400000):
+    """Wall-clock time to r < tol per case: plain FP64 cold start (one case at a
+    time, a sample of n_seq cases) against batched FP32 bulk + learned warm
+    start (n_batch held-out cases in one batch, inference included)."""
+    import numpy as np
+    import torch
+    from paper_2308_15407_amd import learned as LW
+    path = LW.default_weights_path()
+    if not os.path.exists(path):
+        return {"skipped": "no trained warm-start weights in the package"}
+    model = LW.WarmStartModel.load(path)
+    held = LW.draw_cases(100001, n_batch, kn_min=0.05, nx=64, qx_max=8)
+    seq_t, seq_st = [], []
+    for c in held[:n_seq]:
+        _, _, st, res, wall = LW.solve_steady([c], tol, max_steps, check_every=100, precision=0)
+        seq_t.append(wall)
+        seq_st.append(int(st[0]))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = model.predict(held)
+    fields = [LW.warm_fields(c, p) for c, p in zip(held, pred)]
+    t_pred = time.perf_counter() - t0
+    _, _, st, res, wall, nfb = LW.solve_steady_warm(held, fields, tol, max_steps, check_every=100, precision=1)
+    _, _, st_c, res_c, wall_c = LW.solve_steady(held, tol, max_steps, check_every=100, precision=1)
+    plain = float(np.mean(seq_t))
+    learned = (wall + t_pred) / len(held)
+    return {"workload": "held-out sweep cases (seeds from 100001): Nx=64 uniform, Q_x^h<=8 x 4 x 4, Kn>=0.05, tol %g"
+                        % tol,
+            "plain_fp64_cold_s_per_case": round(plain, 4), "plain_sample_cases": len(seq_t),
+            "plain_mean_steps": float(np.mean(seq_st)),
+            "batched_fp32_learned_s_per_case": round(learned, 4), "batched_cases": len(held),
+            "batched_fp32_learned_mean_steps": float(np.mean(st)), "warm_fallbacks": int(nfb),
+            "batched_fp32_cold_s_per_case": round(wall_c / len(held), 4),
+            "batched_fp32_cold_mean_steps": float(np.mean(st_c)),
+            "converged": int(np.sum(res < tol)), "speedup_vs_plain": round(plain / learned, 2)}
 
 
 def main():
@@ -150,6 +204,8 @@ def main():
                 "tiling": {"kx_per_chunk": tileL[0], "waves": tileL[1]},
                 "roofline": roofline(profL, nodesL, prec, "k_update<%s,2>" % ("double" if prec == 0 else "float"), "R2"),
                 "kernel_ms": {"table": round(profL[0], 5), "update": [round(x, 5) for x in profL[1 + 3 * prec:4 + 3 * prec]]}}
+        out["sweep"] = sweep_leg(args.sweep_steps, args.retune)
+        out["time_to_steady"] = time_to_steady_leg(args.tts_batch, args.tts_seq)
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg)
     print(json.dumps(out))
 

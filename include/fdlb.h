@@ -139,6 +139,17 @@ int fdlb_set_state(fdlb_handle h, int c, const double *fields, const double *noi
 int fdlb_get_f(fdlb_handle h, int c, double *host_f);
 int fdlb_set_f(fdlb_handle h, int c, const double *host_f);
 
+/* Promote case c from FP32-bulk to FP64 storage now (no-op for FP64 cases):
+   the FP64 populations are the FP32 state, which holds f minus the case's
+   background populations, plus that background.  Later steps run in FP64.
+   Rebuilds the launch maps (drops captured graphs); synchronises. */
+int fdlb_promote(fdlb_handle h, int c);
+
+/* Stall rule of fdlb_run_to_steady for FP32-bulk cases: a case whose residual
+   has not dropped below 0.9 x its best value for `checks` consecutive checks
+   is promoted to FP64 (default 20; checks >= 1). */
+int fdlb_set_stall_checks(fdlb_handle h, int checks);
+
 /* Precision currently used for the bulk of case c (fdlb_precision). */
 int fdlb_case_precision(fdlb_handle h, int c, int *precision);
 

@@ -457,6 +457,22 @@ extern "C" int fdlb_dt(fdlb_handle h, int c, double *dt) {
   return FDLB_OK;
 }
 
+static int promote_case(fdlb_ctx *h, int c, double mass0);
+
+extern "C" int fdlb_promote(fdlb_handle h, int c) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (h->cases[c].prec == 0) return FDLB_OK;
+  return promote_case(h, c, 0.0);
+}
+
+extern "C" int fdlb_set_stall_checks(fdlb_handle h, int checks) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  if (checks < 1) return fail(FDLB_EINVAL, "stall checks must be >= 1");
+  h->converge_hist = checks;
+  return FDLB_OK;
+}
+
 extern "C" int fdlb_case_precision(fdlb_handle h, int c, int *prec) {
   int r = check_case(h, c);
   if (r) return r;
@@ -490,10 +506,12 @@ extern "C" int fdlb_get_f(fdlb_handle h, int c, double *host_f) {
     HIPCHK(hipMemcpyAsync(host_f, h->hdev[c].f[0][0], n * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   } else {
+    // FP32 storage holds f - bg
     std::vector<float> tmp(n);
     HIPCHK(hipMemcpyAsync(tmp.data(), h->hdev[c].f[1][0], n * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
-    for (size_t i = 0; i < n; i++) host_f[i] = tmp[i];
+    const double *bg = ch.lat.data() + ch.lo.bg;
+    for (size_t i = 0; i < n; i++) host_f[i] = (double)tmp[i] + bg[i / ch.nx];
   }
   return FDLB_OK;
 }
@@ -524,7 +542,9 @@ extern "C" int fdlb_set_f(fdlb_handle h, int c, const double *host_f) {
     HIPCHK(hipMemcpyAsync(h->hdev[c].f[0][0], host_f, n * 8, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   } else {
-    std::vector<float> tmp(host_f, host_f + n);
+    std::vector<float> tmp(n);
+    const double *bg = ch.lat.data() + ch.lo.bg;
+    for (size_t i = 0; i < n; i++) tmp[i] = (float)(host_f[i] - bg[i / ch.nx]);
     HIPCHK(hipMemcpyAsync(h->hdev[c].f[1][0], tmp.data(), n * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
@@ -597,7 +617,7 @@ static int promote_case(fdlb_ctx *h, int c, double mass0) {
   HIPCHK(hipStreamSynchronize(h->stream));
   double mass = 0;
   for (int i = 0; i < ch.nx; i++) mass += mom[i] * ch.jac[i] * ch.deta;
-  HIPCHK(launch_convert(0, d.f[1][0], d.f[0][0], n, h->stream));
+  HIPCHK(launch_promote(h->d_cases, c, n, h->stream));
   if (mass0 > 0 && mass > 0) HIPCHK(launch_scale(d.f[0][0], mass0 / mass, n, h->stream));
   ch.prec = 0;
   d.prec = 0;

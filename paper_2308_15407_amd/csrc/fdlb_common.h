@@ -17,6 +17,7 @@ constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
 constexpr int CTILE = FDLB_CTILE;  // cells per table block
 constexpr int CHALO = 6;       // moment halo of a table block
 constexpr int NRAW = 9;        // raw moment sums per cell
+constexpr int ROWBUF = 72;     // LDS row buffer of an interior update tile (69 cells, padded); two per wave
 
 // Offsets (in doubles) of the lattice constants of one case.
 struct LatOff {
@@ -30,6 +31,10 @@ struct LatOff {
   int fdw;          // one-sided 7-point first-derivative weights, rows for cells 0,1,2 [3*7]
   int phi;          // moment weights of every velocity [K][8] (64-byte rows): px, py, px^2, px py,
                     // py^2, pz^2, px |p|^2, py |p|^2 (the weight of the density sum is 1)
+  int bg;           // background populations [K] (the case's uniform initial state); FP32 storage
+                    // holds f - bg
+  int kbg;          // body-force kernel applied to the background [K]
+  int bgm;          // raw moment sums of the background [NRAW]
   int total;
 };
 

@@ -57,5 +57,7 @@ hipError_t launch_zero_resid(const CaseDev *cases, int ncases, hipStream_t s);
 hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStream_t s);
 hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream_t s);
 hipError_t launch_scale(void *x, double a, size_t n, hipStream_t s);
+// FP32 deviation storage of case c -> FP64 populations (adds the background)
+hipError_t launch_promote(const CaseDev *cases, int c, size_t n, hipStream_t s);
 
 }  // namespace fdlb

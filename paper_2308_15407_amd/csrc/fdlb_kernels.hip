@@ -114,7 +114,9 @@ __device__ __forceinline__ T weno_face(const T v0, const T v1, const T v2, const
   const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
   T w1 = (T)0.1 * p23 * p23, w2 = (T)0.6 * p13 * p13, w3 = d3 * p12 * p12;
   T ws = w1 + w2 + w3;
-  if (ws == (T)0) {
+  // smallest normal number of T: below it the reciprocal of ws is not finite
+  const T tiny = sizeof(T) == 4 ? (T)1.17549435e-38f : (T)2.2250738585072014e-308;
+  if (!(ws >= tiny)) {
     // two or more indicators vanish (or the products underflow)
     const bool z1 = b1 == (T)0, z2 = b2 == (T)0, z3 = !drop3 && b3 == (T)0;
     if (z1 || z2 || z3) {
@@ -156,7 +158,9 @@ __device__ void wall_block(const CaseDev &c, int wall, int gin) {
     double f0, f1, f2;
     if (wall == 0) { f0 = row[0]; f1 = row[1]; f2 = row[2]; }
     else { f0 = row[nx - 1]; f1 = row[nx - 2]; f2 = row[nx - 3]; }
-    acc += p * (f2 * (1.0 / 3.0) - f1 * (7.0 / 6.0) + f0 * (11.0 / 6.0));
+    // the extrapolation weights sum to one: the background passes through
+    const double bgk = sizeof(T) == 4 ? c.lat[c.lo.bg + kap] : 0.0;
+    acc += p * (bgk + (f2 * (1.0 / 3.0) - f1 * (7.0 / 6.0) + f0 * (11.0 / 6.0)));
   }
   red[threadIdx.x] = acc;
   __syncthreads();
@@ -244,6 +248,11 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
           for (int m = 0; m < NRAW; m++) v[m] = pp[(size_t)m * nx];
 #pragma unroll
           for (int m = 0; m < NRAW; m++) S[m] += v[m];
+        }
+        if (sizeof(T) == 4) {
+          // FP32 storage holds f - bg: add the background's raw sums
+#pragma unroll
+          for (int m = 0; m < NRAW; m++) S[m] += lat[lo.bgm + m];
         }
         n = S[0];
         ux = S[1] / n; uy = S[2] / n;
@@ -485,6 +494,8 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 template <typename T, int STAGE, bool FORCE>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_UPDATE_WPE, 8))) k_update(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
   extern __shared__ double lds_dyn[];
+  // FP32 storage holds the deviation from the case's background populations
+  constexpr bool DF = sizeof(T) == 4;
   const int4 bm = map[blockIdx.x];
   if (bm.x < 0) return;
   const CaseDev &c = cases[bm.x];
@@ -609,7 +620,13 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       __syncthreads();
     }
     const bool interior = tlds && c0 >= 3 && c0 + 66 <= nx;
+    // interior tiles: per-wave LDS row buffer after the tables, and the lane
+    // offsets of the row load (own cell c0-3+lane) and its 5-cell right halo
+    T *sRow = sX + 4 * c.kxc * 64 + wv * 2 * ROWBUF;
+    const unsigned oa = (unsigned)(c0 - 3 + lane) * (unsigned)sizeof(T);
+    const unsigned oh = lane < 5 ? (unsigned)(c0 + 61 + lane) * (unsigned)sizeof(T) : 0x80000000u;
     const CAS double *__restrict__ phi = (const CAS double *)(c.lat + c.lo.phi);
+    const CAS double *__restrict__ bgc = (const CAS double *)(c.lat + c.lo.bg);
     typedef T T4 __attribute__((ext_vector_type(4)));
     const unsigned rowbytes = (unsigned)nx * (unsigned)sizeof(T);
     // global loads of a row (stencil of the stage input and f^n) are issued
@@ -628,8 +645,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       auto load = [&](int r, Row &d) {
         const int kap = kap_base + r;
         const auto rs = rsrc_of(gin + (size_t)kap * tstride, rowbytes);
-        d.t0 = bld<T>(rs, o0); d.t1 = bld<T>(rs, o1); d.t2 = bld<T>(rs, o2); d.t3 = bld<T>(rs, o3);
-        d.t4 = bld<T>(rs, o4);
+        if (WALL) {
+          d.t0 = bld<T>(rs, o0); d.t1 = bld<T>(rs, o1); d.t2 = bld<T>(rs, o2); d.t3 = bld<T>(rs, o3);
+          d.t4 = bld<T>(rs, o4);
+        } else {
+          // cells c0-3+lane, and c0+61..c0+65 on lanes 0..4 (other lanes read
+          // past the row range: no memory access, zero)
+          d.t0 = bld<T>(rs, oa);
+          d.t1 = bld<T>(rs, oh);
+        }
         if (STAGE != 1) d.fnv = bld<T>(rsrc_of(fn + (size_t)kap * tstride, rowbytes), bc);
       };
       auto compute = [&](int r, const Row &d) {
@@ -650,10 +674,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
           y0 = ldb(y, bc); y1 = ldb(y + ya, bc); y2 = ldb(y + 2 * ya, bc); y3 = ldb(y + 3 * ya, bc);
           x0 = ldb(x, bc); x1 = ldb(x + xa, bc); x2 = ldb(x + 2 * xa, bc); x3 = ldb(x + 3 * xa, bc);
         }
-        T v0 = d.t0, v1 = d.t1, v2 = d.t2, cen;
+        T v0, v1, v2, v3, v4, cen;
         T fh;
         if (WALL) {
-          const T fw = (T)((POS ? nwl : nwr) * (double)(POS ? gwL : gwR)[kap]);
+          v0 = d.t0; v1 = d.t1; v2 = d.t2;
+          const T fw = (T)((POS ? nwl : nwr) * (double)(POS ? gwL : gwR)[kap] - (DF ? bgc[kap] : 0.0));
           if (g0) v0 = fw;
           if (g1) v1 = fw;
           if (g2) v2 = fw;
@@ -661,11 +686,26 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
           const T w = weno_face<T>(v0, v1, v2, d.t3, d.t4, mode == 3 ? 0 : mode);
           fh = (mode == 3) ? fw : w;
         } else {
-          cen = POS ? d.t3 : v2;
-          fh = weno_face<T>(v0, v1, v2, d.t3, d.t4, 0);
+          // the row's 69 cells pass through one of this wave's two LDS row
+          // buffers (alternating by row); the five stencil values are shifted
+          // reads of it.  Lanes read what other lanes wrote: the wave-scope
+          // release/acquire pair orders the writes before the reads, and the
+          // alternation keeps the next-but-one row's writes behind this
+          // row's reads (they are separated by the next row's pair).
+          T *rb = sRow + (r & 1) * ROWBUF;
+          rb[lane] = d.t0;
+          if (lane < 5) rb[64 + lane] = d.t1;
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+          if (POS) { v0 = rb[lane]; v1 = rb[lane + 1]; v2 = rb[lane + 2]; v3 = rb[lane + 3]; v4 = rb[lane + 4]; }
+          else { v0 = rb[lane + 5]; v1 = rb[lane + 4]; v2 = rb[lane + 3]; v3 = rb[lane + 2]; v4 = rb[lane + 1]; }
+          cen = POS ? v3 : v2;
+          fh = weno_face<T>(v0, v1, v2, v3, v4, 0);
         }
         const T fr = __shfl_down(fh, 1, 64);
-        const T F = x0 * y0 + x1 * y1 + x2 * y2 + x3 * y3;
+        T F = x0 * y0 + x1 * y1 + x2 * y2 + x3 * y3;
+        if (DF) F -= (T)bgc[kap];
         const T L = (-(T)pxd * dxi) * (fr - fh) + (F - cen) * itau;
         const T adv1 = cen + dt * L;
         T o;
@@ -726,7 +766,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       for (int ky = 0; ky < MAXQY; ky++) {
         if (ky < qy) {
           const int kap = (kx * qy + ky) * qz + kz;
-          const T fw = (T)(nw * (double)gw[kap]);
+          const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
           const T fh = face(gin + (size_t)kap * tstride, pos, fw, cen[ky]);
           const T fr = __shfl_down(fh, 1, 64);
           adv[ky] = -(T)pxd * dxi * (fr - fh);
@@ -742,7 +782,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
 #pragma unroll
           for (int k2 = 0; k2 < MAXQY; k2++)
             if (k2 < qy) sf += (T)km[k2] * cen[k2];
-          const T F = target(yz, X0, X1, X2, X3);
+          T F = target(yz, X0, X1, X2, X3);
+          if (DF) { sf += (T)lat[c.lo.kbg + kap]; F -= (T)lat[c.lo.bg + kap]; }
           finish(kap, ky, kz, pxd, cen[ky], adv[ky] - ay * sf + (F - cen[ky]) * itau);
         }
       }
@@ -779,6 +820,7 @@ __global__ void __launch_bounds__(512) k_fill(const CaseDev *__restrict__ cases,
     for (int a = 0; a < 4; a++)
       F += (double)tX[(size_t)(a * nkx + kx) * nx + jc] * (double)tYZ[(size_t)(a * qyz + yz) * nx + jc];
     if (use_noise) F *= 1.0 + c.noise[(size_t)kap * nx + jc];
+    if (sizeof(T) == 4) F -= lat[c.lo.bg + kap];   // FP32 storage: deviation from the background
     const T o = (T)F;
     if (is_cell) {
       f[(size_t)kap * nx + j] = o;
@@ -838,6 +880,17 @@ __global__ void k_scale(double *__restrict__ x, double a, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) x[i] *= a;
 }
 
+// FP32 deviation storage of case c -> FP64 populations (f = bg + g)
+__global__ void k_promote(const CaseDev *__restrict__ cases, int ci) {
+  const CaseDev &c = cases[ci];
+  const float *g = (const float *)c.f[1][0];
+  double *f = (double *)c.f[0][0];
+  const double *bg = c.lat + c.lo.bg;
+  const size_t n = (size_t)c.K * c.nx;
+  for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+    f[i] = (double)g[i] + bg[i / c.nx];
+}
+
 template <typename S, typename D>
 __global__ void k_convert(const S *__restrict__ src, D *__restrict__ dst, size_t n) {
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
@@ -872,7 +925,7 @@ static void upd(int stage, dim3 g, dim3 b, size_t lds, hipStream_t s, const Case
 
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds) {
   const size_t part = (size_t)waves * NRAW * 64 * sizeof(double);
-  const size_t tab = tlds ? (size_t)4 * (qyz + kxc) * 64 * (prec == 0 ? 8 : 4) : 0;
+  const size_t tab = tlds ? ((size_t)4 * (qyz + kxc) * 64 + (size_t)waves * 2 * ROWBUF) * (prec == 0 ? 8 : 4) : 0;
   return part > tab ? part : tab;
 }
 
@@ -919,6 +972,13 @@ hipError_t launch_convert(int dir, const void *src, void *dst, size_t n, hipStre
     hipLaunchKernelGGL((k_convert<float, double>), dim3(blocks), dim3(256), 0, s, (const float *)src, (double *)dst, n);
   else
     hipLaunchKernelGGL((k_convert<double, float>), dim3(blocks), dim3(256), 0, s, (const double *)src, (float *)dst, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_promote(const CaseDev *cases, int c, size_t n, hipStream_t s) {
+  const int blocks = (int)((n + 255) / 256 < 4096 ? (n + 255) / 256 : 4096);
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_promote, dim3(blocks), dim3(256), 0, s, cases, c);
   return hipGetLastError();
 }
 

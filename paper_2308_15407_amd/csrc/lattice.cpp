@@ -205,6 +205,9 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   o.fdw = off; off += 3 * 7;
   off = (off + 7) & ~7;   // 64-byte aligned rows (one scalar load per velocity)
   o.phi = off; off += c.K * 8;
+  o.bg = off; off += c.K;
+  o.kbg = off; off += c.K;
+  o.bgm = off; off += NRAW;
   o.total = off;
   c.lat.assign(off, 0.0);
   double *L = c.lat.data();
@@ -332,6 +335,30 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
           if ((wall == 0 && pxv > 0) || (wall == 1 && pxv < 0)) den += fabs(pxv) * v;
         }
     c.wallD[wall] = den;
+  }
+  // background: the projected uniform initial state n_init f^MB(u_y = uy_init, T = t_init)
+  {
+    std::vector<double> X(2 * Q), Y(c.qy), Z(c.qz);
+    host_half_table(L, o, Q, 0.0, p.t_init, 0, X.data());
+    host_full_table(&L[o.Hy], c.qy, p.uy_init, p.t_init, 0, Y.data());
+    host_full_table(&L[o.Hz], c.qz, 0.0, p.t_init, 0, Z.data());
+    for (int m = 0; m < NRAW; m++) L[o.bgm + m] = 0;
+    for (int kx = 0; kx < 2 * Q; kx++)
+      for (int ky = 0; ky < c.qy; ky++)
+        for (int kz = 0; kz < c.qz; kz++) {
+          const int kap = (kx * c.qy + ky) * c.qz + kz;
+          const double b = p.n_init * X[kx] * Y[ky] * Z[kz];
+          L[o.bg + kap] = b;
+          L[o.bgm] += b;
+          for (int m = 1; m < NRAW; m++) L[o.bgm + m] += L[o.phi + kap * 8 + m - 1] * b;
+        }
+    for (int kx = 0; kx < 2 * Q; kx++)
+      for (int ky = 0; ky < c.qy; ky++)
+        for (int kz = 0; kz < c.qz; kz++) {
+          double sf = 0;
+          for (int k2 = 0; k2 < c.qy; k2++) sf += L[o.kmat + ky * c.qy + k2] * L[o.bg + (kx * c.qy + k2) * c.qz + kz];
+          L[o.kbg + (kx * c.qy + ky) * c.qz + kz] = sf;
+        }
   }
   return 0;
 }

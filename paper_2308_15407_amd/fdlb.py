@@ -20,7 +20,8 @@ MOMENT_NAMES = ("n", "ux", "uy", "T", "qx", "qy", "Pxx", "Pxy", "Pyy", "Pzz")
 # every symbol declared in include/fdlb.h
 EXPORTS = ("fdlb_workspace_bytes", "fdlb_case_info", "fdlb_case_lattice", "fdlb_case_grid", "fdlb_init",
            "fdlb_step", "fdlb_moments", "fdlb_grid_coords", "fdlb_lattice", "fdlb_dt", "fdlb_run_to_steady",
-           "fdlb_residual", "fdlb_set_state", "fdlb_get_f", "fdlb_set_f", "fdlb_case_precision",
+           "fdlb_residual", "fdlb_set_state", "fdlb_get_f", "fdlb_set_f", "fdlb_promote",
+           "fdlb_set_stall_checks", "fdlb_case_precision",
            "fdlb_set_tiling", "fdlb_set_graph_steps", "fdlb_profile", "fdlb_copy_probe", "fdlb_destroy",
            "fdlb_last_error", "fdlb_mlp_workspace_bytes", "fdlb_mlp_init", "fdlb_mlp_num_params",
            "fdlb_mlp_set_params", "fdlb_mlp_get_params", "fdlb_mlp_forward", "fdlb_mlp_loss_grad",
@@ -93,6 +94,8 @@ def lib():
         L.fdlb_get_f.argtypes = [P, I, dp]
         L.fdlb_set_f.argtypes = [P, I, dp]
         L.fdlb_case_precision.argtypes = [P, I, C.POINTER(I)]
+        L.fdlb_promote.argtypes = [P, I]
+        L.fdlb_set_stall_checks.argtypes = [P, I]
         L.fdlb_set_tiling.argtypes = [P, I, I]
         L.fdlb_set_graph_steps.argtypes = [P, I]
         L.fdlb_profile.argtypes = [P, I, dp]
@@ -233,6 +236,14 @@ def fdlb_get_f(h, c, K, nx):
 def fdlb_set_f(h, c, f):
     f = np.ascontiguousarray(f, dtype=np.float64)
     _chk(lib().fdlb_set_f(h, c, _dptr(f)))
+
+
+def fdlb_promote(h, c):
+    _chk(lib().fdlb_promote(h, c))
+
+
+def fdlb_set_stall_checks(h, checks):
+    _chk(lib().fdlb_set_stall_checks(h, checks))
 
 
 def fdlb_case_precision(h, c):

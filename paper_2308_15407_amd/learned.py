@@ -155,12 +155,14 @@ def draw_cases(seed0, n, r_min=2.0, kn_min=0.05, nx=64, qx_max=8):
 def solve_steady(cases, tol, max_steps, check_every=200, precision=1, fields=None, log=None):
     """Batched solve of `cases` (all in one launch map) to the residual tol.
     Returns (moments list, grids, steps, residuals, wall seconds); a case that
-    diverged has a non-finite residual (the others still run to the end)."""
+    diverged has a non-finite residual (the others still run to the end).
+    The wall time covers setting the warm state and the run, not the set-up."""
     import torch
     from .solver import Solver
     cs = [dict({k: v for k, v in c.items() if not k.startswith("_")}, precision=precision) for c in cases]
-    t0 = time.perf_counter()
     s = Solver(cs)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()   # one-time set-up (lattice, tables, upload) excluded
     if fields is not None:
         for i, f in enumerate(fields):
             if f is not None:

@@ -69,6 +69,12 @@ class Solver:
     def run_to_steady(self, tol=1e-8, max_steps=10 ** 6, check_every=100):
         return F.fdlb_run_to_steady(self.handle, self.ncases, tol, max_steps, check_every)
 
+    def promote(self, c=0):
+        F.fdlb_promote(self.handle, c)
+
+    def set_stall_checks(self, checks):
+        F.fdlb_set_stall_checks(self.handle, checks)
+
     def set_state(self, c, fields, noise=None):
         F.fdlb_set_state(self.handle, c, fields, noise)
 

@@ -66,3 +66,17 @@ def test_workspace_grows_with_cases():
     a = F.fdlb_workspace_bytes([I.config("C1")])
     b = F.fdlb_workspace_bytes([I.config("C1"), I.config("C2")])
     assert b > a > 0
+
+
+def test_sweep_batch_is_seeded_and_valid():
+    """The sweep batch: 256 accepted draws (R >= 2), identical on every call,
+    spanning the generator's grid sizes and half-range orders."""
+    from paper_2308_15407_amd import fdlb as F, sweep
+    a = sweep.sweep_cases(256)
+    b = sweep.sweep_cases(256)
+    assert len(a) == 256 and a == b
+    assert all(F.fdlb_case_info(c)["R"] >= 2.0 for c in a)
+    assert {c["nx"] for c in a} == {64, 128, 256, 512}
+    assert {c["qx_half"] for c in a} == {4, 8, 12, 16}
+    assert all(c["precision"] == 1 and c["qy"] == 4 and c["qz"] == 4 for c in a)
+    assert {c["flow"] for c in a} == {0, 1, 2}
