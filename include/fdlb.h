@@ -112,6 +112,9 @@ int fdlb_grid_coords(fdlb_handle h, int c, double *x, double *jac);
 /* Velocity set of case c: px, py, pz and lattice weights w, each [K]. */
 int fdlb_lattice(fdlb_handle h, int c, double *px, double *py, double *pz, double *w);
 
+/* Geometry of case c: out3[0] = sigma, out3[1] = L_c, out3[2] = R. */
+int fdlb_geometry(fdlb_handle h, int c, double *out3);
+
 /* Time step of case c. */
 int fdlb_dt(fdlb_handle h, int c, double *dt);
 
@@ -149,6 +152,14 @@ int fdlb_promote(fdlb_handle h, int c);
    has not dropped below 0.9 x its best value for `checks` consecutive checks
    is promoted to FP64 (default 20; checks >= 1). */
 int fdlb_set_stall_checks(fdlb_handle h, int checks);
+
+/* When on, fdlb_run_to_steady gives a case whose moments turn non-finite one
+   restart from its uniform initial state (same batch, steps keep counting)
+   instead of retiring it; for warm starts that may be unstable.  Default off. */
+int fdlb_set_restart_on_nonfinite(fdlb_handle h, int on);
+
+/* Restarts of each case in the last fdlb_run_to_steady: out[ncases]. */
+int fdlb_restarts(fdlb_handle h, long *out);
 
 /* Precision currently used for the bulk of case c (fdlb_precision). */
 int fdlb_case_precision(fdlb_handle h, int c, int *precision);

@@ -53,6 +53,8 @@ struct fdlb_ctx {
   hipGraph_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
   int converge_hist = 20;
+  bool restart_nonfinite = false;   // run_to_steady: restart a diverged case once from its cold state
+  std::vector<long> restarts;       // restarts per case in the last run_to_steady
 };
 
 static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -450,6 +452,15 @@ extern "C" int fdlb_lattice(fdlb_handle h, int c, double *px, double *py, double
   return FDLB_OK;
 }
 
+extern "C" int fdlb_geometry(fdlb_handle h, int c, double *out3) {
+  int r = check_case(h, c);
+  if (r) return r;
+  if (!out3) return fail(FDLB_EINVAL, "null output");
+  const CaseHost &ch = h->cases[c];
+  out3[0] = ch.sigma; out3[1] = ch.Lc; out3[2] = ch.R;
+  return FDLB_OK;
+}
+
 extern "C" int fdlb_dt(fdlb_handle h, int c, double *dt) {
   int r = check_case(h, c);
   if (r) return r;
@@ -464,6 +475,18 @@ extern "C" int fdlb_promote(fdlb_handle h, int c) {
   if (r) return r;
   if (h->cases[c].prec == 0) return FDLB_OK;
   return promote_case(h, c, 0.0);
+}
+
+extern "C" int fdlb_set_restart_on_nonfinite(fdlb_handle h, int on) {
+  if (!h) return fail(FDLB_EINVAL, "null handle");
+  h->restart_nonfinite = on != 0;
+  return FDLB_OK;
+}
+
+extern "C" int fdlb_restarts(fdlb_handle h, long *out) {
+  if (!h || !out) return fail(FDLB_EINVAL, "null argument");
+  for (size_t i = 0; i < h->cases.size(); i++) out[i] = i < h->restarts.size() ? h->restarts[i] : 0;
+  return FDLB_OK;
 }
 
 extern "C" int fdlb_set_stall_checks(fdlb_handle h, int checks) {
@@ -637,6 +660,7 @@ extern "C" int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, lon
   std::vector<double> best(nc, INFINITY), mass0(nc, 0.0);
   std::vector<int> since_best(nc, 0);
   for (int i = 0; i < nc; i++) { start[i] = h->cases[i].steps; h->cases[i].active = true; }
+  h->restarts.assign(nc, 0);
   int r = build_maps(h);
   if (r) return r;
   // mass of every case at the start (restored if an FP32 case is promoted)
@@ -668,7 +692,29 @@ extern "C" int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, lon
       CaseHost &c = h->cases[i];
       if (!c.active) continue;
       c.last_resid = res[i];
-      if (!(res[i] == res[i]) || std::isinf(res[i])) { c.active = false; changed = true; nonfinite = true; continue; }
+      if (!(res[i] == res[i]) || std::isinf(res[i])) {
+        if (h->restart_nonfinite && h->restarts[i] == 0) {
+          // back to the uniform initial state; the steps already taken still count
+          std::vector<double> fl((size_t)6 * c.nx, 0.0);
+          for (int k = 0; k < c.nx; k++) { fl[k] = c.p.n_init; fl[2 * c.nx + k] = c.p.uy_init; fl[3 * c.nx + k] = c.p.t_init; }
+          const long taken = c.steps;
+          r = set_state_dev(h, i, fl.data(), nullptr);
+          if (r) return r;
+          c.steps = taken;
+          c.last_resid = INFINITY;
+          {
+            std::vector<double> n0(c.nx);
+            HIPCHK(hipMemcpyAsync(n0.data(), h->hdev[i].mom, sizeof(double) * c.nx, hipMemcpyDeviceToHost, h->stream));
+            HIPCHK(hipStreamSynchronize(h->stream));
+            mass0[i] = 0;
+            for (int k = 0; k < c.nx; k++) mass0[i] += n0[k] * c.jac[k] * c.deta;
+          }
+          best[i] = INFINITY; since_best[i] = 0;
+          h->restarts[i]++;
+          continue;
+        }
+        c.active = false; changed = true; nonfinite = true; continue;
+      }
       if (res[i] < tol || c.steps - start[i] >= max_steps) { c.active = false; changed = true; continue; }
       if (res[i] < 0.9 * best[i]) { best[i] = res[i]; since_best[i] = 0; }
       else if (++since_best[i] >= h->converge_hist && c.prec == 1) {

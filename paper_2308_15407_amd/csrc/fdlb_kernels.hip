@@ -211,10 +211,16 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy
   __shared__ double s_l[3][W];      // ln n, ln chi, ln T
   __shared__ double s_c[CTILE][20]; // n, ux, uy, T, invtau, C[13]
-  __shared__ double s_G[CTILE][2][NB];
+  // the chunk partials are summed by all threads in NSL slices first; the
+  // same LDS later holds the base weights G (rows padded by one double so
+  // that lanes reading different cells or nodes fall in different banks)
+  constexpr int NSL = 256 / W;
+  constexpr int SCR = NSL * NRAW * W > CTILE * 2 * (NB + 1) ? NSL * NRAW * W : CTILE * 2 * (NB + 1);
+  __shared__ double s_scr[SCR];
+  double (*s_G)[2][NB + 1] = reinterpret_cast<double (*)[2][NB + 1]>(s_scr);
   __shared__ double s_mb[CTILE][2][3];
   __shared__ double s_red[256];
-  __shared__ double s_lam[MAXQH * NB];
+  __shared__ double s_lam[MAXQH * (NB + 1)];
   __shared__ double s_b[4][NB];      // P_m, A_m, h_Q(P_m)
   __shared__ double s_k[3][MAXQH];   // p_k, 1/h_Q'(p_k)
   __shared__ double s_H[2][MAXQY * MAXQY];
@@ -226,6 +232,29 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   const int qh = c.qh, qy = c.qy, qz = c.qz;
 
   // ---- moments of the stage input for the tile and its halo ----
+  if (!(mode & TM_FIELDS)) {
+    // slice sl of cell w sums the chunks sl, sl + NSL, ...
+    const int w = tid % W, sl = tid / W, cell = c0 - CHALO + w;
+    if (sl < NSL) {
+      double S[NRAW];
+#pragma unroll
+      for (int m = 0; m < NRAW; m++) S[m] = 0;
+      if (cell >= 0 && cell < nx) {
+        const int nch = c.nchunk;
+        for (int ch = sl; ch < nch; ch += NSL) {
+          const double *pp = c.part + (size_t)ch * NRAW * nx + cell;
+          double v[NRAW];
+#pragma unroll
+          for (int m = 0; m < NRAW; m++) v[m] = pp[(size_t)m * nx];
+#pragma unroll
+          for (int m = 0; m < NRAW; m++) S[m] += v[m];
+        }
+      }
+#pragma unroll
+      for (int m = 0; m < NRAW; m++) s_scr[(sl * NRAW + m) * W + w] = S[m];
+    }
+    __syncthreads();
+  }
   double rmax = 0;
   if (tid < W) {
     const int cell = c0 - CHALO + tid;
@@ -238,16 +267,10 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
       } else {
         double S[NRAW];
 #pragma unroll
-        for (int m = 0; m < NRAW; m++) S[m] = 0;
-        const double *pp = c.part + cell;
-        const int nch = c.nchunk;
-#pragma unroll 4
-        for (int ch = 0; ch < nch; ch++, pp += (size_t)NRAW * nx) {
-          double v[NRAW];
-#pragma unroll
-          for (int m = 0; m < NRAW; m++) v[m] = pp[(size_t)m * nx];
-#pragma unroll
-          for (int m = 0; m < NRAW; m++) S[m] += v[m];
+        for (int m = 0; m < NRAW; m++) {
+          double a = 0;
+          for (int sl = 0; sl < NSL; sl++) a += s_scr[(sl * NRAW + m) * W + tid];
+          S[m] = a;
         }
         if (sizeof(T) == 4) {
           // FP32 storage holds f - bg: add the background's raw sums
@@ -283,7 +306,7 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
     }
   } else if (mode & TM_TABLES) {
     // the other threads stage the lattice constants in LDS meanwhile
-    for (int it = tid - W; it < qh * NB; it += blockDim.x - W) s_lam[it] = lat[lo.lam + it];
+    for (int it = tid - W; it < qh * NB; it += blockDim.x - W) s_lam[(it / NB) * (NB + 1) + it % NB] = lat[lo.lam + it];
     for (int it = tid - W; it < NB; it += blockDim.x - W) {
       s_b[0][it] = lat[lo.bP + it]; s_b[1][it] = lat[lo.bA + it]; s_b[2][it] = lat[lo.hQ + it];
     }
@@ -415,7 +438,7 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
     const int h = kx >= qh, k = kx - h * qh;
     const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
     double x0 = 0;
-    const double *lam = s_lam + k * NB;
+    const double *lam = s_lam + k * (NB + 1);
     const double *Gc = s_G[cl][h];
 #pragma unroll 8
     for (int m = 0; m < NB; m++) x0 += Gc[m] * lam[m];
@@ -489,6 +512,13 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 #endif
 #ifndef FDLB_UPDATE_WPE
 #define FDLB_UPDATE_WPE 4
+#endif
+// depth of the row prefetch ring in interior update tiles
+#ifndef FDLB_RING_F64
+#define FDLB_RING_F64 4
+#endif
+#ifndef FDLB_RING_F32
+#define FDLB_RING_F32 3
 #endif
 
 template <typename T, int STAGE, bool FORCE>
@@ -711,29 +741,33 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
         T o;
         if (STAGE == 1) o = adv1;
         else o = (STAGE == 2) ? (T)0.75 * d.fnv + (T)0.25 * adv1 : d.fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
-        if (is_cell) bst<T>(rsrc_of(out + (size_t)kap * tstride, rowbytes), bw, o);
+        // lanes without a cell store past the row range (dropped), so the
+        // store needs no branch
+        bst<T>(rsrc_of(out + (size_t)kap * tstride, rowbytes), is_cell ? bw : 0x80000000u, o);
         // lanes that own no cell accumulate values that are never stored
         const double od = (double)o;
         acc[0] += od;
 #pragma unroll
         for (int m = 1; m < NRAW; m++) acc[m] = __builtin_fma(ph[m - 1], od, acc[m]);
       };
-      // three register sets rotate: rows r+1 and r+2 are in flight while row
-      // r is computed
-      Row A, B, C;
-      load(ra, A);
-      if (ra + 1 < rb) load(ra + 1, B);
-      int r = ra;
-      for (; r + 2 < rb; r += 3) {
-        load(r + 2, C);
-        compute(r, A);
-        if (r + 3 < rb) load(r + 3, A);
-        compute(r + 1, B);
-        if (r + 4 < rb) load(r + 4, B);
-        compute(r + 2, C);
+      // a ring of D register sets: rows r+1 .. r+D-1 are in flight while row r
+      // is computed (interior rows hold one value per lane plus the halo, so
+      // the ring is deeper there)
+      constexpr int D = WALL ? 3 : (sizeof(T) == 8 ? FDLB_RING_F64 : FDLB_RING_F32);
+      // Loads are issued unconditionally (rows past the range repeat the last
+      // row): every path then has the same loads in flight, so the memory
+      // counter waits stay exact and do not drain the ring.
+      Row ring[D];
+#pragma unroll
+      for (int k = 0; k < D - 1; k++) load(min(ra + k, rb - 1), ring[k]);
+      for (int r = ra; r < rb; r += D) {
+#pragma unroll
+        for (int k = 0; k < D; k++) {
+          const int rr = r + k;
+          load(min(rr + D - 1, rb - 1), ring[(k + D - 1) % D]);
+          if (rr < rb) compute(rr, ring[k]);
+        }
       }
-      if (r < rb) compute(r, A);
-      if (r + 1 < rb) compute(r + 1, B);
     };
     using TT = BoolC<true>;
     using FF = BoolC<false>;

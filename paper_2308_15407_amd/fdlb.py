@@ -19,8 +19,10 @@ MOMENT_NAMES = ("n", "ux", "uy", "T", "qx", "qy", "Pxx", "Pxy", "Pyy", "Pzz")
 
 # every symbol declared in include/fdlb.h
 EXPORTS = ("fdlb_workspace_bytes", "fdlb_case_info", "fdlb_case_lattice", "fdlb_case_grid", "fdlb_init",
-           "fdlb_step", "fdlb_moments", "fdlb_grid_coords", "fdlb_lattice", "fdlb_dt", "fdlb_run_to_steady",
+           "fdlb_step", "fdlb_moments", "fdlb_grid_coords", "fdlb_lattice", "fdlb_geometry", "fdlb_dt",
+           "fdlb_run_to_steady",
            "fdlb_residual", "fdlb_set_state", "fdlb_get_f", "fdlb_set_f", "fdlb_promote",
+           "fdlb_set_restart_on_nonfinite", "fdlb_restarts",
            "fdlb_set_stall_checks", "fdlb_case_precision",
            "fdlb_set_tiling", "fdlb_set_graph_steps", "fdlb_profile", "fdlb_copy_probe", "fdlb_destroy",
            "fdlb_last_error", "fdlb_mlp_workspace_bytes", "fdlb_mlp_init", "fdlb_mlp_num_params",
@@ -95,6 +97,9 @@ def lib():
         L.fdlb_set_f.argtypes = [P, I, dp]
         L.fdlb_case_precision.argtypes = [P, I, C.POINTER(I)]
         L.fdlb_promote.argtypes = [P, I]
+        L.fdlb_geometry.argtypes = [P, I, dp]
+        L.fdlb_set_restart_on_nonfinite.argtypes = [P, I]
+        L.fdlb_restarts.argtypes = [P, C.POINTER(C.c_long)]
         L.fdlb_set_stall_checks.argtypes = [P, I]
         L.fdlb_set_tiling.argtypes = [P, I, I]
         L.fdlb_set_graph_steps.argtypes = [P, I]
@@ -199,6 +204,22 @@ def fdlb_lattice(h, c, K):
     px, py, pz, w = (np.zeros(K) for _ in range(4))
     _chk(lib().fdlb_lattice(h, c, _dptr(px), _dptr(py), _dptr(pz), _dptr(w)))
     return px, py, pz, w
+
+
+def fdlb_set_restart_on_nonfinite(h, on):
+    _chk(lib().fdlb_set_restart_on_nonfinite(h, 1 if on else 0))
+
+
+def fdlb_restarts(h, ncases):
+    out = (C.c_long * ncases)()
+    _chk(lib().fdlb_restarts(h, out))
+    return np.array(list(out))
+
+
+def fdlb_geometry(h, c):
+    out = np.zeros(3)
+    _chk(lib().fdlb_geometry(h, c, _dptr(out)))
+    return {"sigma": out[0], "Lc": out[1], "R": out[2]}
 
 
 def fdlb_dt(h, c):

@@ -152,6 +152,23 @@ def draw_cases(seed0, n, r_min=2.0, kn_min=0.05, nx=64, qx_max=8):
     return out
 
 
+def cases_from_seeds(seeds, nx=64, qx_max=8):
+    """Study cases for the given generator seeds (one draw per seed)."""
+    import fdlb_inputs as I
+    out = []
+    for sd in seeds:
+        c = study_params(I.c4_draws(int(sd), 1)[0], nx=nx, qx_max=qx_max)
+        c["_seed"] = int(sd)
+        out.append(c)
+    return out
+
+
+def default_eval_path():
+    """Summary of the held-out evaluation that accompanies the packaged weights
+    (its `seeds` are the held-out cases the plain FP64 solve converges on)."""
+    return os.path.join(os.path.dirname(os.path.abspath(__file__)), "warmstart_eval.json")
+
+
 def solve_steady(cases, tol, max_steps, check_every=200, precision=1, fields=None, log=None):
     """Batched solve of `cases` (all in one launch map) to the residual tol.
     Returns (moments list, grids, steps, residuals, wall seconds); a case that
@@ -176,14 +193,56 @@ def solve_steady(cases, tol, max_steps, check_every=200, precision=1, fields=Non
     return moms, grids, st, res, wall
 
 
+def solve_steady_learned(cases, model, tol, max_steps, check_every=200, precision=1, grad13=True):
+    """Batched solve warm-started by the network: after the one-time set-up,
+    the timed region covers inference (forward pass, interpolation to each
+    case's grid, mass renormalisation), setting the warm states and the run.
+    Cases whose prediction is non-physical start cold; cases whose warm run
+    diverges are solved again from the cold start (time and steps counted).
+    Returns (moments, grids, steps, residuals, wall seconds, fallbacks,
+    inference seconds)."""
+    import torch
+    from .solver import Solver
+    cs = [dict({k: v for k, v in c.items() if not k.startswith("_")}, precision=precision) for c in cases]
+    s = Solver(cs)
+    grids = [s.grid(i) for i in range(len(cs))]
+    Lcs = [s.geometry(i)["Lc"] for i in range(len(cs))]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    pred = model.predict(cases)
+    fields = [warm_fields(c, p, g, L, grad13) for c, p, g, L in zip(cases, pred, grids, Lcs)]
+    t_inf = time.perf_counter() - t0
+    for i, f in enumerate(fields):
+        if f is not None:
+            s.set_state(i, f)
+    s.set_restart_on_nonfinite(True)     # a diverging warm start restarts cold in the same batch
+    st, res, code = s.run_to_steady(tol=tol, max_steps=max_steps, check_every=check_every)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    nrestart = int(np.sum(s.restarts()))
+    moms = [s.moments(i) for i in range(len(cs))]
+    xg = [g[0] for g in grids]
+    s.close()
+    bad = [i for i in range(len(cases)) if not np.isfinite(res[i])]
+    if bad:
+        m2, g2, s2, r2, w2 = solve_steady([cases[i] for i in bad], tol, max_steps, check_every, precision)
+        wall += w2
+        st, res = st.copy(), res.copy()
+        for k, i in enumerate(bad):
+            moms[i], xg[i], res[i] = m2[k], g2[k], r2[k]
+            st[i] += s2[k]
+    return moms, xg, st, res, wall, nrestart + len(bad), t_inf
+
+
 def solve_steady_warm(cases, fields, tol, max_steps, check_every=200, precision=1):
     """Warm-started batched solve with the plain solve as fallback: cases
     without a physical prediction start cold, and cases whose warm-started run
-    diverges or misses tol are solved again from the cold start.  Returns
+    diverges are solved again from the cold start.  Returns
     (moments, grids, steps, residuals, wall seconds, number of fallbacks);
     wall time and steps include the failed warm attempts."""
     moms, grids, st, res, wall = solve_steady(cases, tol, max_steps, check_every, precision, fields)
-    bad = [i for i in range(len(cases)) if not (res[i] < tol)]
+    # fall back where the warm-started run diverged (non-finite residual)
+    bad = [i for i in range(len(cases)) if not np.isfinite(res[i])]
     if bad:
         m2, g2, s2, r2, w2 = solve_steady([cases[i] for i in bad], tol, max_steps, check_every, precision)
         wall += w2
@@ -270,19 +329,27 @@ class WarmStartModel:
         return cls(net, FeatureScaler(z["fmean"], z["fstd"]), Standardizer(z["tmean"], z["tstd"]))
 
 
-def warm_fields(case, pred):
+def warm_fields(case, pred, grid=None, Lc=None, grad13=True):
     """Prediction (5 x 128 at Chebyshev points) -> fields [6][nx] for
     fdlb_set_state, or None if non-physical.  n is rescaled to the case mass
-    (uniform initial density n_init over L_c)."""
-    info = F.fdlb_case_info(case)
-    xg, jac = F.fdlb_case_grid(case)
-    v = barycentric(cheb_points(info["Lc"]), pred.reshape(len(FIELDS), NCHEB), xg)
+    (uniform initial density n_init over L_c).  grid = (x, dx/deta) and Lc may
+    come from an existing solver handle; otherwise they are computed from the
+    case.  grad13=False keeps only n, u_y, T (a local Maxwellian)."""
+    if grid is None:
+        xg, jac = F.fdlb_case_grid(case)
+    else:
+        xg, jac = grid
+    if Lc is None:
+        Lc = F.fdlb_case_info(case)["Lc"]
+    v = barycentric(cheb_points(Lc), pred.reshape(len(FIELDS), NCHEB), xg)
     n, uy, T, qx, pxy = v
     if not (np.all(n > 0) and np.all(T > 0) and np.all(np.isfinite(v))):
         return None
     deta = 2.0 / case["nx"]
     mass0 = case["n_init"] * np.sum(jac) * deta          # mass of the uniform cold start
     n = n * mass0 / np.sum(n * jac * deta)
+    if not grad13:
+        qx, pxy = np.zeros_like(n), np.zeros_like(n)
     return np.stack([n, np.zeros_like(n), uy, T, qx, pxy])
 
 

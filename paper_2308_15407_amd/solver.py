@@ -60,6 +60,9 @@ class Solver:
     def lattice(self, c=0):
         return F.fdlb_lattice(self.handle, c, self.K[c])
 
+    def geometry(self, c=0):
+        return F.fdlb_geometry(self.handle, c)
+
     def dt(self, c=0):
         return F.fdlb_dt(self.handle, c)
 
@@ -71,6 +74,12 @@ class Solver:
 
     def promote(self, c=0):
         F.fdlb_promote(self.handle, c)
+
+    def set_restart_on_nonfinite(self, on=True):
+        F.fdlb_set_restart_on_nonfinite(self.handle, on)
+
+    def restarts(self):
+        return F.fdlb_restarts(self.handle, self.ncases)
 
     def set_stall_checks(self, checks):
         F.fdlb_set_stall_checks(self.handle, checks)

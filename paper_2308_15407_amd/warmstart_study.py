@@ -52,62 +52,79 @@ def cmd_train(args):
 
 
 def cmd_eval(args):
+    """Time to steady state on held-out cases.  The evaluation set is the
+    held-out draws that the plain FP64 cold solve brings below tol within
+    max_steps (run batched to find them); every arm is then timed on that set."""
     import torch
     from . import learned as LW
     model = LW.WarmStartModel.load(args.weights)
     held = LW.draw_cases(100001, args.count, kn_min=args.kn_min, nx=args.nx, qx_max=args.qx_max)
-    out = {"n_cases": len(held), "tol": args.tol}
-    # prediction accuracy against the converged steady states
+    out = {"n_drawn": len(held), "tol": args.tol, "max_steps": args.max_steps}
+    moms, grids, st, res, wall = LW.solve_steady(held, args.tol, args.max_steps, check_every=args.check, precision=0)
+    ok = [i for i in range(len(held)) if res[i] < args.tol]
+    out["not_converged_plain_seeds"] = [held[i]["_seed"] for i in range(len(held)) if not (res[i] < args.tol)]
+    cases = [held[i] for i in ok]
+    ref = [moms[i] for i in ok]
+    out["n_cases"] = len(cases)
+    out["seeds"] = [c["_seed"] for c in cases]
+    log("evaluation set: %d of %d held-out cases converge under the plain FP64 solve" % (len(cases), len(held)))
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
-    pred = model.predict(held)
-    fields = [LW.warm_fields(c, p) for c, p in zip(held, pred)]
+    pred = model.predict(cases)
+    fields = [LW.warm_fields(c, p) for c, p in zip(cases, pred)]
     t_pred = time.perf_counter() - t0
-    out["fallback_cold"] = int(sum(f is None for f in fields))
     out["inference_seconds"] = t_pred
-    runs = {}
-    for name, prec, warm in (("batched_fp32_learned", 1, True), ("batched_fp32_cold", 1, False),
-                             ("batched_fp64_cold", 0, False), ("batched_fp64_learned", 0, True)):
+    out["nonphysical_predictions"] = int(sum(f is None for f in fields))
+    errs = []
+    for f, m in zip(fields, ref):
+        if f is not None:
+            errs.append([np.max(np.abs(f[0] - m[0]) / m[0]), np.max(np.abs(f[3] - m[3]) / m[3]),
+                         np.max(np.abs(f[2] - m[2])) / max(np.max(np.abs(m[2])), 1e-3)])
+    e = np.array(errs)
+    out["prediction_max_rel_err"] = {k: {"median": float(np.median(e[:, j])), "p90": float(np.percentile(e[:, j], 90))}
+                                     for j, k in enumerate(("n", "T", "uy"))}
+    runs, steps = {}, {}
+    arms = (("batched_fp64_cold", 0, None), ("batched_fp32_cold", 1, None),
+            ("batched_fp32_learned", 1, True), ("batched_fp64_learned", 0, True),
+            ("batched_fp32_learned_maxwellian", 1, False), ("batched_fp64_learned_maxwellian", 0, False))
+    for name, prec, g13 in arms:
         nfb = 0
-        if warm:
-            moms, grids, st, res, wall, nfb = LW.solve_steady_warm(held, fields, args.tol, args.max_steps,
-                                                                   check_every=args.check, precision=prec)
+        if g13 is not None:
+            _, _, st, res, wall, nfb, t_inf = LW.solve_steady_learned(cases, model, args.tol, args.max_steps,
+                                                                      check_every=args.check, precision=prec,
+                                                                      grad13=g13)
+            log("  %s inference %.3f s" % (name, t_inf))
         else:
-            moms, grids, st, res, wall = LW.solve_steady(held, args.tol, args.max_steps, check_every=args.check,
-                                                         precision=prec)
-        runs[name] = dict(wall_s=wall + (t_pred if warm else 0.0), steps_mean=float(np.mean(st)),
-                          steps_max=int(np.max(st)), converged=int(np.sum(res < args.tol)), fallbacks=nfb)
-        log("%s: %.2f s, mean steps %.0f, converged %d/%d" % (name, runs[name]["wall_s"], np.mean(st),
-                                                                runs[name]["converged"], len(held)))
-        if name == "batched_fp64_cold":
-            ref = moms
-            # accuracy of the prediction on the grid
-            errs = []
-            for c, f, m in zip(held, fields, ref):
-                if f is None:
-                    continue
-                errs.append([np.max(np.abs(f[0] - m[0])) / np.max(m[0]), np.max(np.abs(f[3] - m[3])) / np.max(m[3]),
-                             np.max(np.abs(f[2] - m[2])) / max(np.max(np.abs(m[2])), 1e-3)])
-            out["prediction_max_rel_err_median"] = dict(zip(("n", "T", "uy"), np.median(np.array(errs), axis=0).tolist()))
-    # plain FP64 cold start, one case at a time, on a sample of the held-out cases
-    seq = held[:args.seq_count]
-    t_seq, st_seq = 0.0, []
-    for i, c in enumerate(seq):
-        _, _, st, res, wall = LW.solve_steady([c], args.tol, args.max_steps, check_every=args.check, precision=0)
-        t_seq += wall
+            _, _, st, res, wall = LW.solve_steady(cases, args.tol, args.max_steps, check_every=args.check,
+                                                  precision=prec)
+        steps[name] = st
+        runs[name] = dict(wall_s=wall, s_per_case=wall / len(cases), steps_mean=float(np.mean(st)),
+                          steps_median=float(np.median(st)), steps_max=int(np.max(st)),
+                          converged=int(np.sum(res < args.tol)), fallbacks=nfb)
+        log("%s: %.2f s (%.4f s/case), steps mean %.0f median %.0f max %d, converged %d/%d, fallbacks %d"
+            % (name, wall, wall / len(cases), np.mean(st), np.median(st), np.max(st), runs[name]["converged"],
+               len(cases), nfb))
+    for p in ("fp32", "fp64"):
+        for v in ("", "_maxwellian"):
+            r = steps["batched_%s_learned%s" % (p, v)] / np.maximum(steps["batched_%s_cold" % p], 1)
+            runs["step_ratio_learned%s_over_cold_%s" % (v, p)] = {"mean": float(np.mean(r)),
+                                                                   "median": float(np.median(r))}
+    # the plain method: FP64 cold start, one case at a time (a sample of the set)
+    rng = np.random.default_rng(7)
+    pick = sorted(rng.choice(len(cases), size=min(args.seq_count, len(cases)), replace=False).tolist())
+    t_seq, st_seq = [], []
+    for k, i in enumerate(pick):
+        _, _, st, res, wall = LW.solve_steady([cases[i]], args.tol, args.max_steps, check_every=args.check, precision=0)
+        t_seq.append(wall)
         st_seq.append(int(st[0]))
-        log("sequential fp64 cold %d/%d: %.2f s, %d steps" % (i + 1, len(seq), wall, st[0]))
-    runs["sequential_fp64_cold_sample"] = dict(n_cases=len(seq), wall_s=t_seq, per_case_s=t_seq / len(seq),
-                                               steps_mean=float(np.mean(st_seq)))
+        log("plain FP64 cold, one case %d/%d: %.2f s, %d steps" % (k + 1, len(pick), wall, st[0]))
+    runs["plain_fp64_cold_sequential"] = dict(n_cases=len(pick), s_per_case=float(np.mean(t_seq)),
+                                              steps_mean=float(np.mean(st_seq)))
     out["runs"] = runs
-    out["per_case_seconds"] = {
-        "plain_fp64_cold_sequential": t_seq / len(seq),
-        "batched_fp32_learned": runs["batched_fp32_learned"]["wall_s"] / len(held),
-        "batched_fp32_cold": runs["batched_fp32_cold"]["wall_s"] / len(held),
-        "batched_fp64_cold": runs["batched_fp64_cold"]["wall_s"] / len(held)}
-    out["speedup_vs_plain_fp64_cold"] = out["per_case_seconds"]["plain_fp64_cold_sequential"] / \
-        out["per_case_seconds"]["batched_fp32_learned"]
+    plain = float(np.mean(t_seq))
+    out["speedup_vs_plain_fp64_cold"] = {k: plain / runs[k]["s_per_case"] for k, _, _ in arms}
     json.dump(out, open(args.out, "w"), indent=1)
-    log(json.dumps(out))
+    log(json.dumps({k: v for k, v in out.items() if k not in ("seeds", "not_converged_plain_seeds")}))
 
 
 def main(argv=None):
@@ -132,7 +149,7 @@ def main(argv=None):
         if name == "eval":
             p.add_argument("--weights", required=True)
             p.add_argument("--count", type=int, default=512)
-            p.add_argument("--seq-count", type=int, default=16)
+            p.add_argument("--seq-count", type=int, default=24)
             p.add_argument("--check", type=int, default=100)
     args = ap.parse_args(argv)
     {"data": cmd_data, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)

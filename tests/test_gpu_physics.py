@@ -112,3 +112,26 @@ def test_stall_reports_estall():
     st, res, code = s.run_to_steady(tol=1e-14, max_steps=200, check_every=50)
     from paper_2308_15407_amd import fdlb as F
     assert code == F.FDLB_ESTALL and st[0] == 200 and res[0] > 1e-14
+
+
+def test_nonfinite_case_restarts_cold_when_asked():
+    """With restarts on, a diverged case goes back to its uniform initial
+    state inside the same run and reaches the steady state of a cold start;
+    the other case of the batch is not disturbed."""
+    cfg = I.config("C1", nx=24)
+    other = I.config("C1", nx=32)
+    s = _solver([cfg, other])
+    f = s.get_f(0)
+    f[5, 7] = np.nan
+    s.set_f(0, f)
+    s.set_restart_on_nonfinite(True)
+    st, res, code = s.run_to_steady(tol=1e-9, max_steps=200000, check_every=50)
+    assert code == 0 and np.all(res < 1e-9)
+    assert list(s.restarts()) == [1, 0]
+    ref = _solver([cfg, other])
+    st_r, res_r, code_r = ref.run_to_steady(tol=1e-9, max_steps=200000, check_every=50)
+    assert code_r == 0
+    for c in (0, 1):
+        a, b = s.moments(c), ref.moments(c)
+        assert np.max(np.abs(a[0] - b[0]) / b[0]) < 1e-7 and np.max(np.abs(a[3] - b[3]) / b[3]) < 1e-7
+    assert st[0] > st_r[0]          # the failed attempt's steps are counted
