@@ -172,10 +172,11 @@ int fdlb_set_tiling(fdlb_handle h, int kx_per_chunk, int waves_per_block);
 /* Capture nsteps steps in a HIP graph that fdlb_step replays (0 disables). */
 int fdlb_set_graph_steps(fdlb_handle h, int nsteps);
 
-/* Measurement: average device time in ms of each kernel of one step, from
-   HIP events on the caller's stream around nrep back-to-back launches of that
-   kernel alone.  ms_out[7] = table pass, update stages 1-3 (FP64 cases),
-   update stages 1-3 (FP32-bulk cases).  Advances the state by one step. */
+/* Measurement: runs nrep ordinary steps with HIP events on the caller's
+   stream around every table and update launch, and returns the mean device
+   time in ms per launch as the kernels run in sequence: ms_out[7] = table pass
+   (summed over launch groups), update stages 1-3 of FP64 cases, update stages
+   1-3 of FP32-bulk cases.  Advances the state by nrep steps (synchronises). */
 int fdlb_profile(fdlb_handle h, int nrep, double *ms_out);
 
 /* Measurement: plain device-to-device copy of `bytes` (a multiple of 32) on

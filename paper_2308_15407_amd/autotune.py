@@ -10,7 +10,9 @@ import os
 
 import torch
 
-CACHE = os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json")
+# decisions cache (FDLB_TUNING_CACHE overrides the location)
+CACHE = os.environ.get("FDLB_TUNING_CACHE",
+                       os.path.join(os.path.dirname(os.path.abspath(__file__)), "tuning_cache.json"))
 
 
 def _key(solver):

@@ -774,45 +774,46 @@ extern "C" int fdlb_case_grid(const fdlb_params *p, double *x, double *jac) {
 extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
   if (!h || !ms_out || nrep <= 0) return fail(FDLB_EINVAL, "bad profile arguments");
   for (int i = 0; i < 7; i++) ms_out[i] = 0;
-  hipEvent_t e0, e1;
-  HIPCHK(hipEventCreate(&e0));
-  HIPCHK(hipEventCreate(&e1));
-  auto timed = [&](auto &&launch, double *out) -> int {
-    int r = launch();
-    if (r) return r;
-    HIPCHK(hipEventRecord(e0, h->stream));
-    for (int k = 0; k < nrep; k++) { r = launch(); if (r) return r; }
-    HIPCHK(hipEventRecord(e1, h->stream));
-    HIPCHK(hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCHK(hipEventElapsedTime(&ms, e0, e1));
-    *out = ms / nrep;
-    return FDLB_OK;
-  };
+  // nrep ordinary steps; every table and update launch records events at its
+  // own start and end (hipExtLaunchKernel), so the durations are the kernels'
+  // as they run in sequence, without the dispatch gaps between them
+  hipEvent_t ev[3][4][4];
+  for (auto &a : ev)
+    for (auto &b : a)
+      for (auto &e : b) HIPCHK(hipEventCreate(&e));
+  double tab[4] = {0, 0, 0, 0}, upd[4][3] = {};
   int r = FDLB_OK;
-  const int full = TM_PARTIALS | TM_TABLES | TM_WALLS | TM_WRITE_MOM;
-  double tab = 0;
-  for (int G = 0; G < 4 && !r; G++) {
-    if (h->nU[G] == 0) continue;
-    const int P = G >> 1;
-    double t = 0;
-    r = timed([&]() -> int { HIPCHK(launch_table(P, h->d_cases, h->d_mapT[G], h->nT[G], full, 0, h->stream)); return 0; }, &t);
-    tab += t;
-    for (int stage = 1; stage <= 3 && !r; stage++) {
-      if (stage > 1)  // tables of the new stage input
-        HIPCHK(launch_table(P, h->d_cases, h->d_mapT[G], h->nT[G], full & ~TM_WRITE_MOM, stage - 1, h->stream));
-      double u = 0;
-      r = timed([&]() -> int { HIPCHK(launch_update(P, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream)); return 0; }, &u);
-      ms_out[1 + 3 * P + (stage - 1)] += u;
-    }
+  for (int k = 0; k < nrep && !r; k++) {
+    for (int stage = 1; stage <= 3 && !r; stage++)
+      for (int G = 0; G < 4 && !r; G++) {
+        if (h->nU[G] == 0) continue;
+        const int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
+        hipEvent_t *e = ev[stage - 1][G];
+        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->stream, e[0], e[1]));
+        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream,
+                             e[2], e[3]));
+      }
+    HIPCHK(hipStreamSynchronize(h->stream));
+    for (int stage = 0; stage < 3; stage++)
+      for (int G = 0; G < 4; G++) {
+        if (h->nU[G] == 0) continue;
+        float t1 = 0, t2 = 0;
+        HIPCHK(hipEventElapsedTime(&t1, ev[stage][G][0], ev[stage][G][1]));
+        HIPCHK(hipEventElapsedTime(&t2, ev[stage][G][2], ev[stage][G][3]));
+        tab[G] += t1;
+        upd[G][stage] += t2;
+      }
   }
-  ms_out[0] = tab;
-  (void)hipEventDestroy(e0);
-  (void)hipEventDestroy(e1);
-  if (r) return r;
+  for (auto &a : ev)
+    for (auto &b : a)
+      for (auto &e : b) (void)hipEventDestroy(e);
+  for (int G = 0; G < 4; G++) {
+    if (h->nU[G] == 0) continue;
+    ms_out[0] += tab[G] / (3.0 * nrep);
+    for (int stage = 0; stage < 3; stage++) ms_out[1 + 3 * (G >> 1) + stage] += upd[G][stage] / nrep;
+  }
   for (auto &c : h->cases)
-    if (c.active) c.steps += 1;
-  HIPCHK(hipStreamSynchronize(h->stream));
+    if (c.active) c.steps += nrep;
   return FDLB_OK;
 }
 

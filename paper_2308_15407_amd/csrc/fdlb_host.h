@@ -41,14 +41,15 @@ enum {
 };
 
 // kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
+// e0/e1 (optional): events recorded at the kernel's own start and end (timing)
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
-                        hipStream_t s);
+                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // dynamic LDS of an update launch: partial sums of the waves, or the staged
 // projection tables of a tile when tlds (at most UPDATE_LDS_MAX bytes)
 constexpr size_t UPDATE_LDS_MAX = 65536;
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds);
 hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
-                         int force, size_t lds, hipStream_t s);
+                         int force, size_t lds, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_fill(int prec, const CaseDev *cases, const int *map, int nblocks, int waves, int use_noise,
                        hipStream_t s);
 hipError_t launch_partials(int prec, const CaseDev *cases, const int *map, int nblocks, int waves,

@@ -16,6 +16,7 @@
 //              the target, applies the RK3 combination (eq:rk3) and
 //              accumulates the FP64 raw moment sums of its output, reduced
 //              across the block's waves in LDS into per-chunk partials.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "fdlb_common.h"
@@ -940,21 +941,28 @@ __global__ void __launch_bounds__(256) k_copy_probe(const double4 *__restrict__ 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// plain launch, or (timing) with events recorded at the kernel's own start and end
+template <typename K, typename... A>
+static void launch_k(K kern, dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1, A... args) {
+  if (e0) hipExtLaunchKernelGGL(kern, g, b, (uint32_t)lds, s, e0, e1, 0u, args...);
+  else hipLaunchKernelGGL(kern, g, b, lds, s, args...);
+}
+
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
-                        hipStream_t s) {
+                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
-  if (prec == 0)
-    hipLaunchKernelGGL(k_table<double>, dim3(nblocks), dim3(256), 0, s, cases, (const int4 *)map, mode, gin);
-  else
-    hipLaunchKernelGGL(k_table<float>, dim3(nblocks), dim3(256), 0, s, cases, (const int4 *)map, mode, gin);
+  const int4 *m = (const int4 *)map;
+  if (prec == 0) launch_k(k_table<double>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
+  else launch_k(k_table<float>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
   return hipGetLastError();
 }
 
 template <typename T, bool FORCE>
-static void upd(int stage, dim3 g, dim3 b, size_t lds, hipStream_t s, const CaseDev *cases, const int4 *map) {
-  if (stage == 1) hipLaunchKernelGGL((k_update<T, 1, FORCE>), g, b, lds, s, cases, map);
-  else if (stage == 2) hipLaunchKernelGGL((k_update<T, 2, FORCE>), g, b, lds, s, cases, map);
-  else hipLaunchKernelGGL((k_update<T, 3, FORCE>), g, b, lds, s, cases, map);
+static void upd(int stage, dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
+                const CaseDev *cases, const int4 *map) {
+  if (stage == 1) launch_k(k_update<T, 1, FORCE>, g, b, lds, s, e0, e1, cases, map);
+  else if (stage == 2) launch_k(k_update<T, 2, FORCE>, g, b, lds, s, e0, e1, cases, map);
+  else launch_k(k_update<T, 3, FORCE>, g, b, lds, s, e0, e1, cases, map);
 }
 
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds) {
@@ -964,13 +972,13 @@ size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds) {
 }
 
 hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
-                         int force, size_t lds, hipStream_t s) {
+                         int force, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
   if (lds > UPDATE_LDS_MAX || lds < (size_t)waves * NRAW * 64 * sizeof(double)) return hipErrorInvalidValue;
   const dim3 g(nblocks), b(64 * waves);
   const int4 *m = (const int4 *)map;
-  if (prec == 0) { if (force) upd<double, true>(stage, g, b, lds, s, cases, m); else upd<double, false>(stage, g, b, lds, s, cases, m); }
-  else { if (force) upd<float, true>(stage, g, b, lds, s, cases, m); else upd<float, false>(stage, g, b, lds, s, cases, m); }
+  if (prec == 0) { if (force) upd<double, true>(stage, g, b, lds, s, e0, e1, cases, m); else upd<double, false>(stage, g, b, lds, s, e0, e1, cases, m); }
+  else { if (force) upd<float, true>(stage, g, b, lds, s, e0, e1, cases, m); else upd<float, false>(stage, g, b, lds, s, e0, e1, cases, m); }
   return hipGetLastError();
 }
 

@@ -135,3 +135,40 @@ def test_nonfinite_case_restarts_cold_when_asked():
         a, b = s.moments(c), ref.moments(c)
         assert np.max(np.abs(a[0] - b[0]) / b[0]) < 1e-7 and np.max(np.abs(a[3] - b[3]) / b[3]) < 1e-7
     assert st[0] > st_r[0]          # the failed attempt's steps are counted
+
+
+def test_profile_runs_ordinary_steps_and_times_each_kernel():
+    """fdlb_profile advances the state exactly like nrep ordinary steps and
+    reports positive in-sequence kernel times for both storage precisions."""
+    cfgs = [I.config("C1", nx=40), dict(I.config("C1", nx=40), precision=1)]
+    a = _solver(cfgs)
+    b = _solver(cfgs)
+    ms = a.profile(3)
+    b.step(3)
+    for c in (0, 1):
+        assert np.array_equal(a.moments(c), b.moments(c))
+        assert np.array_equal(a.get_f(c), b.get_f(c))
+    assert ms[0] > 0 and all(t > 0 for t in ms[1:7])
+
+
+def test_autotuner_picks_a_candidate_and_results_do_not_depend_on_tiling(tmp_path, monkeypatch):
+    """The autotuner times the candidate (kx per chunk, waves) shapes, applies
+    the fastest and caches it; any tiling gives the same moments up to the
+    summation order of the chunk partials."""
+    from paper_2308_15407_amd import autotune
+    monkeypatch.setattr(autotune, "CACHE", str(tmp_path / "cache.json"))
+    cfgs = [I.config("C2", nx=96, qx_half=6), dict(I.config("C1", nx=40), precision=1)]
+    s = _solver(cfgs)
+    pick = autotune.tune(s, trial_steps=4, use_cache=True)
+    assert pick in autotune.candidates(s)
+    assert autotune.tune(s, use_cache=True) == pick          # served from the cache
+    ref = _solver(cfgs)
+    ref.set_tiling(1, 1)
+    s2 = _solver(cfgs)
+    s2.set_tiling(*pick)
+    s2.step(30)
+    ref.step(30)
+    for c in (0, 1):
+        a, b = s2.moments(c), ref.moments(c)
+        tol = 1e-12 if c == 0 else 1e-6
+        assert np.max(np.abs(a[0] - b[0]) / b[0]) < tol and np.max(np.abs(a[3] - b[3]) / b[3]) < tol
