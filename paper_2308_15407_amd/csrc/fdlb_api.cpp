@@ -71,13 +71,14 @@ static void case_sizes(const CaseHost &c, size_t *sz) {
   for (int i = 0; i < A_COUNT; i++) sz[i] = 0;
   sz[A_LAT] = c.lo.total * 8;
   sz[A_INVDX] = nx * 8;
-  sz[A_F64_0] = sz[A_F64_1] = sz[A_F64_2] = K * nx * 8;
+  const size_t nxp = c.nxp;
+  sz[A_F64_0] = sz[A_F64_1] = sz[A_F64_2] = K * nxp * 8;
   sz[A_TX64] = 4 * nkx * nx * 8;
   sz[A_TYZ64] = 4 * qyz * nx * 8;
   sz[A_IT64] = nx * 8;
   sz[A_GW64_0] = sz[A_GW64_1] = K * 8;
   if (c.p.precision == FDLB_F32_BULK) {
-    sz[A_F32_0] = sz[A_F32_1] = sz[A_F32_2] = K * nx * 4;
+    sz[A_F32_0] = sz[A_F32_1] = sz[A_F32_2] = K * nxp * 4;
     sz[A_TX32] = 4 * nkx * nx * 4;
     sz[A_TYZ32] = 4 * qyz * nx * 4;
     sz[A_IT32] = nx * 4;
@@ -342,6 +343,7 @@ extern "C" int fdlb_init(const fdlb_params *ps, int ncases, void *dev_ws, size_t
     c.prec = c.p.precision;
     c.active = true;
     d.nx = c.nx; d.qh = c.qh; d.qy = c.qy; d.qz = c.qz; d.K = c.K; d.nkx = 2 * c.qh; d.qyz = c.qy * c.qz;
+    d.nxp = c.nxp;
     d.ntile_u = (c.nx + UTILE - 1) / UTILE; d.ntile_c = (c.nx + CTILE - 1) / CTILE;
     d.collision = c.p.collision; d.j1_shear = c.p.j1_shear;
     d.eta0 = c.p.eta0; d.kn = c.p.kn; d.chi0 = c.chi0; d.pr_fixed = c.p.pr_fixed; d.ay = c.p.ay; d.dt = c.dt;
@@ -524,18 +526,21 @@ extern "C" int fdlb_get_f(fdlb_handle h, int c, double *host_f) {
   if (r) return r;
   if (!host_f) return fail(FDLB_EINVAL, "null output");
   const CaseHost &ch = h->cases[c];
-  const size_t n = (size_t)ch.K * ch.nx;
+  const size_t ns = (size_t)ch.K * ch.nxp;
+  // device rows hold the cells in 64-slot tiles; FP32 storage holds f - bg
+  std::vector<double> dev(ns);
   if (ch.prec == 0) {
-    HIPCHK(hipMemcpyAsync(host_f, h->hdev[c].f[0][0], n * 8, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(hipMemcpyAsync(dev.data(), h->hdev[c].f[0][0], ns * 8, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   } else {
-    // FP32 storage holds f - bg
-    std::vector<float> tmp(n);
-    HIPCHK(hipMemcpyAsync(tmp.data(), h->hdev[c].f[1][0], n * 4, hipMemcpyDeviceToHost, h->stream));
+    std::vector<float> tmp(ns);
+    HIPCHK(hipMemcpyAsync(tmp.data(), h->hdev[c].f[1][0], ns * 4, hipMemcpyDeviceToHost, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
     const double *bg = ch.lat.data() + ch.lo.bg;
-    for (size_t i = 0; i < n; i++) host_f[i] = (double)tmp[i] + bg[i / ch.nx];
+    for (size_t i = 0; i < ns; i++) dev[i] = (double)tmp[i] + bg[i / ch.nxp];
   }
+  for (int k = 0; k < ch.K; k++)
+    for (int i = 0; i < ch.nx; i++) host_f[(size_t)k * ch.nx + i] = dev[(size_t)k * ch.nxp + fslot(i)];
   return FDLB_OK;
 }
 
@@ -560,15 +565,19 @@ extern "C" int fdlb_set_f(fdlb_handle h, int c, const double *host_f) {
   if (r) return r;
   if (!host_f) return fail(FDLB_EINVAL, "null input");
   const CaseHost &ch = h->cases[c];
-  const size_t n = (size_t)ch.K * ch.nx;
+  const size_t ns = (size_t)ch.K * ch.nxp;
+  // cells into their slots (padding slots hold 0); FP32 storage holds f - bg
+  std::vector<double> dev(ns, 0.0);
+  for (int k = 0; k < ch.K; k++)
+    for (int i = 0; i < ch.nx; i++) dev[(size_t)k * ch.nxp + fslot(i)] = host_f[(size_t)k * ch.nx + i];
   if (ch.prec == 0) {
-    HIPCHK(hipMemcpyAsync(h->hdev[c].f[0][0], host_f, n * 8, hipMemcpyHostToDevice, h->stream));
+    HIPCHK(hipMemcpyAsync(h->hdev[c].f[0][0], dev.data(), ns * 8, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   } else {
-    std::vector<float> tmp(n);
+    std::vector<float> tmp(ns);
     const double *bg = ch.lat.data() + ch.lo.bg;
-    for (size_t i = 0; i < n; i++) tmp[i] = (float)(host_f[i] - bg[i / ch.nx]);
-    HIPCHK(hipMemcpyAsync(h->hdev[c].f[1][0], tmp.data(), n * 4, hipMemcpyHostToDevice, h->stream));
+    for (size_t i = 0; i < ns; i++) tmp[i] = (float)(dev[i] - bg[i / ch.nxp]);
+    HIPCHK(hipMemcpyAsync(h->hdev[c].f[1][0], tmp.data(), ns * 4, hipMemcpyHostToDevice, h->stream));
     HIPCHK(hipStreamSynchronize(h->stream));
   }
   bool was = h->hdev[c].active;
@@ -632,7 +641,7 @@ extern "C" int fdlb_residual(fdlb_handle h, double *out) {
 static int promote_case(fdlb_ctx *h, int c, double mass0) {
   CaseHost &ch = h->cases[c];
   CaseDev &d = h->hdev[c];
-  const size_t n = (size_t)ch.K * ch.nx;
+  const size_t n = (size_t)ch.K * ch.nxp;   // slots
   // the FP32 phase conserves mass only to its rounding: restore the mass the
   // case carried when the run started
   std::vector<double> mom((size_t)FDLB_NMOM * ch.nx);

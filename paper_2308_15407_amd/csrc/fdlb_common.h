@@ -19,6 +19,12 @@ constexpr int CHALO = 6;       // moment halo of a table block
 constexpr int NRAW = 9;        // raw moment sums per cell
 constexpr int ROWBUF = 72;     // LDS row buffer of an interior update tile (69 cells, padded); two per wave
 
+// Populations are stored per velocity in 64-slot tiles holding 63 cells each
+// (one padding slot), so that the rows an update tile reads start on a
+// 64-element boundary: cell i lives in slot i + i / 63.
+__host__ __device__ inline int fslot(int cell) { return cell + cell / UTILE; }
+__host__ __device__ inline int fslots(int nx) { return 64 * ((nx + UTILE - 1) / UTILE); }
+
 // Offsets (in doubles) of the lattice constants of one case.
 struct LatOff {
   int px, py, pz;   // node coordinates: [2qh], [qy], [qz]
@@ -41,6 +47,7 @@ struct LatOff {
 // One case as the kernels see it (lives in device memory).
 struct CaseDev {
   int nx, qh, qy, qz, K, nkx, qyz;
+  int nxp;              // slots per velocity row of the population arrays (fslots(nx))
   int nchunk, kxc, ntile_u, ntile_c;
   int prec;             // active storage: 0 double, 1 float
   int collision, j1_shear;
@@ -52,7 +59,7 @@ struct CaseDev {
   double *lat;          // lattice constants
   LatOff lo;
   double *invdx;        // [nx] 1/(J_i deta)
-  void *f[2][3];        // populations f^n, f^(1), f^(2) per storage precision
+  void *f[2][3];        // populations f^n, f^(1), f^(2) per storage precision, [K][nxp] slots
   void *tabX[2];        // n X_a[kx] at [a][kx][cell]
   void *tabYZ[2];       // YZ_a[ky*qz+kz] at [a][yz][cell]
   void *invtau[2];      // [nx]

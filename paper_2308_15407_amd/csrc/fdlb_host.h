@@ -12,6 +12,7 @@ namespace fdlb {
 struct CaseHost {
   fdlb_params p;
   int nx, qh, qy, qz, K;
+  int nxp;                          // slots per population row (fslots(nx))
   double sigma, R, Lc, chi0, deta, dt;
   LatOff lo;
   std::vector<double> lat;          // lattice constants (see LatOff)

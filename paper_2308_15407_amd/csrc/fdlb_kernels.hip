@@ -133,6 +133,34 @@ __device__ __forceinline__ T weno_face(const T v0, const T v1, const T v2, const
   return (mode == 2) ? F1 : r;
 }
 
+// Face value for interior faces (all three candidates, no ghosts).  In FP64
+// the indicators are scaled into [0, 1] and offset by 1e-30, so the weight
+// products neither vanish nor underflow and no branch is needed: a candidate
+// whose indicator is below 1e-30 of the largest is weighted as if it were
+// 1e-30 of it, which changes the face value by ~1e-15 of the local variation.
+// FP32 keeps the exact zero-set rule of weno_face.
+template <typename T>
+__device__ __forceinline__ T weno_face_interior(const T v0, const T v1, const T v2, const T v3, const T v4) {
+  if constexpr (sizeof(T) == 4) {
+    return weno_face<T>(v0, v1, v2, v3, v4, 0);
+  } else {
+    const T F1 = v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0);
+    const T F2 = -v1 * (1.0 / 6.0) + v2 * (5.0 / 6.0) + v3 * (1.0 / 3.0);
+    const T F3 = v2 * (1.0 / 3.0) + v3 * (5.0 / 6.0) - v4 * (1.0 / 6.0);
+    const T a1 = v0 - 2.0 * v1 + v2, c1 = v0 - 4.0 * v1 + 3.0 * v2;
+    const T a2 = v1 - 2.0 * v2 + v3, c2 = v1 - v3;
+    const T a3 = v2 - 2.0 * v3 + v4, c3 = 3.0 * v2 - 4.0 * v3 + v4;
+    T b1 = (13.0 / 12.0) * a1 * a1 + 0.25 * c1 * c1;
+    T b2 = (13.0 / 12.0) * a2 * a2 + 0.25 * c2 * c2;
+    T b3 = (13.0 / 12.0) * a3 * a3 + 0.25 * c3 * c3;
+    const T r = fast_rcp(fmax(fmax(b1, b2), b3) + 1e-300);
+    b1 = b1 * r + 1e-30; b2 = b2 * r + 1e-30; b3 = b3 * r + 1e-30;
+    const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
+    const T w1 = 0.1 * p23 * p23, w2 = 0.6 * p13 * p13, w3 = 0.3 * p12 * p12;
+    return (w1 * F1 + w2 * F2 + w3 * F3) * fast_rcp(w1 + w2 + w3);
+  }
+}
+
 __device__ __forceinline__ double chi_cs(double eta) {
   const double om = 1.0 - eta;
   return 0.5 * (2.0 - eta) / (om * om * om);
@@ -155,10 +183,10 @@ __device__ void wall_block(const CaseDev &c, int wall, int gin) {
     const int kx = (wall == 0 ? qh : 0) + t / qyz;
     const int kap = kx * qyz + t % qyz;
     const double p = c.lat[c.lo.px + kx];
-    const T *row = g + (size_t)kap * nx;
+    const T *row = g + (size_t)kap * c.nxp;
     double f0, f1, f2;
-    if (wall == 0) { f0 = row[0]; f1 = row[1]; f2 = row[2]; }
-    else { f0 = row[nx - 1]; f1 = row[nx - 2]; f2 = row[nx - 3]; }
+    if (wall == 0) { f0 = row[fslot(0)]; f1 = row[fslot(1)]; f2 = row[fslot(2)]; }
+    else { f0 = row[fslot(nx - 1)]; f1 = row[fslot(nx - 2)]; f2 = row[fslot(nx - 3)]; }
     // the extrapolation weights sum to one: the background passes through
     const double bgk = sizeof(T) == 4 ? c.lat[c.lo.bg + kap] : 0.0;
     acc += p * (bgk + (f2 * (1.0 / 3.0) - f1 * (7.0 / 6.0) + f0 * (11.0 / 6.0)));
@@ -549,21 +577,25 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
   const int j = c0 + lane;                       // face j (left face of cell j)
   const bool is_cell = lane < UTILE && j < nx;
   const int jc = min(j, nx - 1);
-  const unsigned bc = (unsigned)jc * (unsigned)sizeof(T);   // byte offsets of this lane's cell
-  const unsigned bw = (unsigned)max(j, 0) * (unsigned)sizeof(T);
+  // byte offsets of this lane's cell: in the [.][cell] tables, and as a slot
+  // of the population rows (read and write)
+  const unsigned bc = (unsigned)jc * (unsigned)sizeof(T);
+  const unsigned bcf = (unsigned)fslot(jc) * (unsigned)sizeof(T);
+  const unsigned bw = (unsigned)fslot(max(j, 0)) * (unsigned)sizeof(T);
   const int kx0 = bm.z * c.kxc, kx1 = min(kx0 + c.kxc, nkx);
   const double nwl = gp<double>(c.nw)[0], nwr = gp<double>(c.nw)[1];
   const T dxi = (T)gp<double>(c.invdx)[jc];
   const T itau = gp<T>(c.invtau[P])[jc];
   (void)itau;
   const T dt = (T)c.dt;
-  const size_t tstride = (size_t)nx;             // row stride of every [.][cell] array
+  const size_t tstride = (size_t)nx;             // row stride of the [.][cell] tables
+  const size_t fstride = (size_t)c.nxp;          // row stride of the population arrays (slots)
   // clamped stencil offsets for both upwind directions and ghost flags
   unsigned op0, op1, op2, op3, op4, on0, on1, on2, on3, on4;
   bool gp0, gp1, gp2, gn2, gn3, gn4;
   {
     const int cp = j - 3, cn = j + 2;
-    auto cl = [&](int x) { return (unsigned)min(max(x, 0), nx - 1) * (unsigned)sizeof(T); };
+    auto cl = [&](int x) { return (unsigned)fslot(min(max(x, 0), nx - 1)) * (unsigned)sizeof(T); };
     op0 = cl(cp); op1 = cl(cp + 1); op2 = cl(cp + 2); op3 = cl(cp + 3); op4 = cl(cp + 4);
     on0 = cl(cn); on1 = cl(cn - 1); on2 = cl(cn - 2); on3 = cl(cn - 3); on4 = cl(cn - 4);
     // ghosts can only appear on the emitting side of the stencil
@@ -581,10 +613,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     T o;
     if (STAGE == 1) o = adv1;
     else {
-      const T fnv = ldb(fn + (size_t)kap * tstride, bc);
+      const T fnv = ldb(fn + (size_t)kap * fstride, bcf);
       o = (STAGE == 2) ? (T)0.75 * fnv + (T)0.25 * adv1 : fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
     }
-    if (is_cell) stb(out + (size_t)kap * tstride, bw, o);
+    if (is_cell) stb(out + (size_t)kap * fstride, bw, o);
     {
       const double pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
       const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
@@ -651,15 +683,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       __syncthreads();
     }
     const bool interior = tlds && c0 >= 3 && c0 + 66 <= nx;
-    // interior tiles: per-wave LDS row buffer after the tables, and the lane
-    // offsets of the row load (own cell c0-3+lane) and its 5-cell right halo
+    // interior tiles: per-wave LDS row buffers after the tables.  The row load
+    // takes the tile's 64 aligned slots (cells c0 .. c0+62 and the padding
+    // slot); a second load brings the halo: cells c0-3 .. c0-1 on lanes 0..2
+    // and c0+63 .. c0+65 on lanes 3..5 (other lanes read past the row: zero)
     T *sRow = sX + 4 * c.kxc * 64 + wv * 2 * ROWBUF;
-    const unsigned oa = (unsigned)(c0 - 3 + lane) * (unsigned)sizeof(T);
-    const unsigned oh = lane < 5 ? (unsigned)(c0 + 61 + lane) * (unsigned)sizeof(T) : 0x80000000u;
+    const unsigned oa = (unsigned)(64 * bm.y + lane) * (unsigned)sizeof(T);
+    const unsigned oh = lane < 3 ? (unsigned)fslot(max(c0 - 3 + lane, 0)) * (unsigned)sizeof(T)
+                                 : (lane < 6 ? (unsigned)fslot(min(c0 + 60 + lane, nx - 1)) * (unsigned)sizeof(T)
+                                             : 0x80000000u);
     const CAS double *__restrict__ phi = (const CAS double *)(c.lat + c.lo.phi);
     const CAS double *__restrict__ bgc = (const CAS double *)(c.lat + c.lo.bg);
     typedef T T4 __attribute__((ext_vector_type(4)));
-    const unsigned rowbytes = (unsigned)nx * (unsigned)sizeof(T);
+    const unsigned rowbytes = (unsigned)c.nxp * (unsigned)sizeof(T);
     // global loads of a row (stencil of the stage input and f^n) are issued
     // two rows ahead; the tables (LDS, short latency) are read at the start of
     // the row's arithmetic
@@ -675,17 +711,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       const int mode = POS ? mode_p : mode_n;
       auto load = [&](int r, Row &d) {
         const int kap = kap_base + r;
-        const auto rs = rsrc_of(gin + (size_t)kap * tstride, rowbytes);
+        const auto rs = rsrc_of(gin + (size_t)kap * fstride, rowbytes);
         if (WALL) {
           d.t0 = bld<T>(rs, o0); d.t1 = bld<T>(rs, o1); d.t2 = bld<T>(rs, o2); d.t3 = bld<T>(rs, o3);
           d.t4 = bld<T>(rs, o4);
         } else {
-          // cells c0-3+lane, and c0+61..c0+65 on lanes 0..4 (other lanes read
-          // past the row range: no memory access, zero)
           d.t0 = bld<T>(rs, oa);
           d.t1 = bld<T>(rs, oh);
         }
-        if (STAGE != 1) d.fnv = bld<T>(rsrc_of(fn + (size_t)kap * tstride, rowbytes), bc);
+        if (STAGE != 1) d.fnv = bld<T>(rsrc_of(fn + (size_t)kap * fstride, rowbytes), bcf);
       };
       auto compute = [&](int r, const Row &d) {
         const int kap = kap_base + r;
@@ -723,16 +757,18 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
           // release/acquire pair orders the writes before the reads, and the
           // alternation keeps the next-but-one row's writes behind this
           // row's reads (they are separated by the next row's pair).
+          // buffer index i holds cell c0-3+i; the padding slot (lane 63) goes
+          // to an unused entry
           T *rb = sRow + (r & 1) * ROWBUF;
-          rb[lane] = d.t0;
-          if (lane < 5) rb[64 + lane] = d.t1;
+          rb[lane < 63 ? lane + 3 : 69] = d.t0;
+          if (lane < 6) rb[lane < 3 ? lane : 63 + lane] = d.t1;
           __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
           __builtin_amdgcn_wave_barrier();
           __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
           if (POS) { v0 = rb[lane]; v1 = rb[lane + 1]; v2 = rb[lane + 2]; v3 = rb[lane + 3]; v4 = rb[lane + 4]; }
           else { v0 = rb[lane + 5]; v1 = rb[lane + 4]; v2 = rb[lane + 3]; v3 = rb[lane + 2]; v4 = rb[lane + 1]; }
           cen = POS ? v3 : v2;
-          fh = weno_face<T>(v0, v1, v2, v3, v4, 0);
+          fh = weno_face_interior<T>(v0, v1, v2, v3, v4);
         }
         const T fr = __shfl_down(fh, 1, 64);
         T F = x0 * y0 + x1 * y1 + x2 * y2 + x3 * y3;
@@ -744,7 +780,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
         else o = (STAGE == 2) ? (T)0.75 * d.fnv + (T)0.25 * adv1 : d.fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
         // lanes without a cell store past the row range (dropped), so the
         // store needs no branch
-        bst<T>(rsrc_of(out + (size_t)kap * tstride, rowbytes), is_cell ? bw : 0x80000000u, o);
+        bst<T>(rsrc_of(out + (size_t)kap * fstride, rowbytes), is_cell ? bw : 0x80000000u, o);
         // lanes that own no cell accumulate values that are never stored
         const double od = (double)o;
         acc[0] += od;
@@ -761,12 +797,21 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       Row ring[D];
 #pragma unroll
       for (int k = 0; k < D - 1; k++) load(min(ra + k, rb - 1), ring[k]);
-      for (int r = ra; r < rb; r += D) {
+      int r = ra;
+      // full trips: straight-line code over D rows, so the scheduler can
+      // overlap the rows' dependent chains
+      for (; r + D <= rb; r += D) {
 #pragma unroll
         for (int k = 0; k < D; k++) {
-          const int rr = r + k;
-          load(min(rr + D - 1, rb - 1), ring[(k + D - 1) % D]);
-          if (rr < rb) compute(rr, ring[k]);
+          load(min(r + k + D - 1, rb - 1), ring[(k + D - 1) % D]);
+          compute(r + k, ring[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < D; k++) {
+        if (r + k < rb) {
+          load(min(r + k + D - 1, rb - 1), ring[(k + D - 1) % D]);
+          compute(r + k, ring[k]);
         }
       }
     };
@@ -802,7 +847,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
         if (ky < qy) {
           const int kap = (kx * qy + ky) * qz + kz;
           const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
-          const T fh = face(gin + (size_t)kap * tstride, pos, fw, cen[ky]);
+          const T fh = face(gin + (size_t)kap * fstride, pos, fw, cen[ky]);
           const T fr = __shfl_down(fh, 1, 64);
           adv[ky] = -(T)pxd * dxi * (fr - fh);
         }
@@ -858,7 +903,7 @@ __global__ void __launch_bounds__(512) k_fill(const CaseDev *__restrict__ cases,
     if (sizeof(T) == 4) F -= lat[c.lo.bg + kap];   // FP32 storage: deviation from the background
     const T o = (T)F;
     if (is_cell) {
-      f[(size_t)kap * nx + j] = o;
+      f[(size_t)kap * c.nxp + fslot(j)] = o;
       const double od = (double)o, pxd = lat[c.lo.px + kx], pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
       const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
       acc[0] += od; acc[1] += pxd * od; acc[2] += pyd * od; acc[3] += pxd * pxd * od; acc[4] += pxd * pyd * od;
@@ -893,7 +938,7 @@ __global__ void __launch_bounds__(512) k_partials(const CaseDev *__restrict__ ca
     const int kx = kx0 + r / qyz, yz = r % qyz, ky = yz / qz, kz = yz % qz;
     const int kap = kx * qyz + yz;
     if (is_cell) {
-      const double od = (double)f[(size_t)kap * nx + jc];
+      const double od = (double)f[(size_t)kap * c.nxp + fslot(jc)];
       const double pxd = lat[c.lo.px + kx], pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
       const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
       acc[0] += od; acc[1] += pxd * od; acc[2] += pyd * od; acc[3] += pxd * pxd * od; acc[4] += pxd * pyd * od;
@@ -921,9 +966,9 @@ __global__ void k_promote(const CaseDev *__restrict__ cases, int ci) {
   const float *g = (const float *)c.f[1][0];
   double *f = (double *)c.f[0][0];
   const double *bg = c.lat + c.lo.bg;
-  const size_t n = (size_t)c.K * c.nx;
+  const size_t n = (size_t)c.K * c.nxp;
   for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
-    f[i] = (double)g[i] + bg[i / c.nx];
+    f[i] = (double)g[i] + bg[i / c.nxp];
 }
 
 template <typename S, typename D>

@@ -185,6 +185,7 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   c.p = p;
   c.nx = p.nx; c.qh = p.qx_half; c.qy = p.qy; c.qz = p.qz;
   c.K = 2 * c.qh * c.qy * c.qz;
+  c.nxp = fslots(c.nx);
   c.sigma = sigma; c.R = R; c.Lc = 1.0 - sigma;
   c.chi0 = chi_cs(p.eta0);
   const int Q = c.qh;
