@@ -460,28 +460,40 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   __syncthreads();
 
   // ---- n X_a[kx] tables ----
+  // one item = one cell and half x a pair of nodes: each base weight read
+  // from LDS feeds two independent dot products
   const int nkx = c.nkx;
   T *tX = (T *)c.tabX[c.prec];
-  for (int it = tid; it < own * nkx; it += blockDim.x) {
-    const int cl = it % own, kx = it / own;     // cell fastest: coalesced stores
-    const int h = kx >= qh, k = kx - h * qh;
+  const int ngrp = (qh + 1) / 2;
+  for (int it = tid; it < own * 2 * ngrp; it += blockDim.x) {
+    const int cl = it % own, rest = it / own, h = rest & 1, k0 = 2 * (rest >> 1);   // cell fastest
     const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
-    double x0 = 0;
-    const double *lam = s_lam + k * (NB + 1);
     const double *Gc = s_G[cl][h];
+    const double *l0 = s_lam + k0 * (NB + 1), *l1 = s_lam + min(k0 + 1, qh - 1) * (NB + 1);
+    double x[2] = {0.0, 0.0};
 #pragma unroll 8
-    for (int m = 0; m < NB; m++) x0 += Gc[m] * lam[m];
-    const double dk = s_k[0][k] - u, ck = s_k[1][k];
+    for (int m = 0; m < NB; m++) {
+      const double g = Gc[m];
+      x[0] += g * l0[m]; x[1] += g * l1[m];
+    }
     const double *mb = s_mb[cl][h];
-    const double X1 = dk * x0 + ck * mb[0];
-    const double X2 = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
-    const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
     const double sg = h ? -1.0 : 1.0, n = s_c[cl][0];
     const size_t i = (size_t)c0 + cl;
-    tX[(size_t)(0 * nkx + kx) * nx + i] = (T)(n * x0);
-    tX[(size_t)(1 * nkx + kx) * nx + i] = (T)(n * sg * X1);
-    tX[(size_t)(2 * nkx + kx) * nx + i] = (T)(n * X2);
-    tX[(size_t)(3 * nkx + kx) * nx + i] = (T)(n * sg * X3);
+#pragma unroll
+    for (int j = 0; j < 2; j++) {
+      const int k = k0 + j;
+      if (k < qh) {
+        const int kx = h * qh + k;
+        const double x0 = x[j], dk = s_k[0][k] - u, ck = s_k[1][k];
+        const double X1 = dk * x0 + ck * mb[0];
+        const double X2 = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
+        const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
+        tX[(size_t)(0 * nkx + kx) * nx + i] = (T)(n * x0);
+        tX[(size_t)(1 * nkx + kx) * nx + i] = (T)(n * sg * X1);
+        tX[(size_t)(2 * nkx + kx) * nx + i] = (T)(n * X2);
+        tX[(size_t)(3 * nkx + kx) * nx + i] = (T)(n * sg * X3);
+      }
+    }
   }
 
   // ---- YZ_a[ky,kz] tables and 1/tau ----

@@ -108,3 +108,33 @@ def test_full_size_c2_and_c3_few_steps():
         s.step(steps)
         o.step(steps)
         _compare(s, o, TOL64, "%s full size %d steps" % (name, steps))
+
+
+def test_sweep_batch_at_full_size_matches_oracle_on_sampled_cases():
+    """The 256-case sweep batch as bench.py runs it (one launch map, FP32 bulk,
+    tiling 8 x 8, graph replay): sampled small cases agree with the FP64
+    oracle to the FP32-bulk tolerances, and with the same case run alone
+    bit for bit."""
+    from paper_2308_15407_amd import sweep
+    from paper_2308_15407_amd.solver import Solver
+    cases = sweep.sweep_cases(256)
+    steps = 40
+    s = Solver(cases, tiling=(8, 8), graph_steps=20)
+    s.step(steps)
+    picks = [i for i, c in enumerate(cases) if c["nx"] == 64 and c["qx_half"] <= 8][:4]
+    assert len(picks) == 4
+    for i in picks:
+        cfg = cases[i]
+        o = O.Oracle(**{k: v for k, v in cfg.items() if k != "precision"})
+        o.step(steps)
+        err = rel_moment_errors(s.moments(i), o.moments())
+        print("sweep case %d" % i, {k: "%.1e" % v for k, v in err.items()}, flush=True)
+        for k in ("n", "uy", "T", "Pxy"):
+            assert err[k] < 1e-5, (i, k, err[k])
+        # 40 steps from rest: u_x and q_x are still forming (channel maxima of
+        # order 1e-3), so their relative errors carry that small scale
+        for k in ("ux", "qx"):
+            assert err[k] < 5e-4, (i, k, err[k])
+        alone = Solver(cfg, tiling=(8, 8))
+        alone.step(steps)
+        assert np.array_equal(alone.moments(0), s.moments(i))
