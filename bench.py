@@ -79,7 +79,7 @@ def measure(cfg, steps, warmup, retune, graph_steps=50):
     from paper_2308_15407_amd.solver import Solver
     from paper_2308_15407_amd import autotune
     s = Solver(cfg)
-    tile = autotune.tune(s, use_cache=not retune)
+    tile = autotune.tune(s, use_cache=True, refresh=retune)
     s.set_graph_steps(graph_steps)
     ms = timed_run(s, steps, warmup)
     cases = cfg if isinstance(cfg, list) else [cfg]

@@ -42,8 +42,10 @@ def time_steps(solver, nsteps):
     return a.elapsed_time(b) / nsteps
 
 
-def tune(solver, trial_steps=20, use_cache=True, verbose=False):
-    """Pick and apply the fastest (kx_per_chunk, waves); returns it."""
+def tune(solver, trial_steps=20, use_cache=True, verbose=False, refresh=False):
+    """Pick and apply the fastest (kx_per_chunk, waves); returns it.  With
+    use_cache a cached decision is reused and a new one is stored; refresh
+    times the candidates again and overwrites the cached decision."""
     key = _key(solver)
     cache = {}
     if use_cache and os.path.exists(CACHE):
@@ -51,7 +53,7 @@ def tune(solver, trial_steps=20, use_cache=True, verbose=False):
             cache = json.load(open(CACHE))
         except ValueError:
             cache = {}
-    if use_cache and key in cache:
+    if use_cache and not refresh and key in cache:
         kxc, waves = cache[key]
         solver.set_tiling(kxc, waves)
         return kxc, waves
