@@ -30,6 +30,12 @@
  * normalisation, projection of the Shakhov/J1 polynomials, wall treatment,
  * stretched grid, residual).
  *
+ * Pins (tests/test_oracle_pins.py) fix the quadratures, projections, chi, tau,
+ * Pr, the force kernel, the target's conservation and balance laws, WENO, FD6,
+ * RK3, Maxwellian invariance, wall mass conservation, symmetry, the dilute
+ * limit and the free-molecular heat flux.  Parity unpinned: dense steady
+ * profiles at finite Kn in general, for which no independent values exist.
+ *
  * Build: gcc -O2 -ffp-contract=off -fPIC -shared fdlb_oracle.c -lquadmath -lm
  */
 #include <math.h>

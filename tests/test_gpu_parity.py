@@ -53,7 +53,7 @@ def test_c1_fourier_bgk_steps(steps):
 
 
 def test_couette_shakhov_stretched_ragged():
-    # 80 cells: two update tiles (63 + 17) and three table tiles (32, 32, 16)
+    # 80 cells: two update tiles (63 + 17) and five table tiles of 16
     cfg = I.config("C2", nx=80, qx_half=6)
     s, o = _pair(cfg, 3)
     s.step(20)
@@ -138,3 +138,24 @@ def test_sweep_batch_at_full_size_matches_oracle_on_sampled_cases():
         alone = Solver(cfg, tiling=(8, 8))
         alone.step(steps)
         assert np.array_equal(alone.moments(0), s.moments(i))
+
+
+@pytest.mark.parametrize("flow,prec", [("C2", 0), ("C3", 0), ("C2", 1)])
+def test_largest_velocity_sets(flow, prec):
+    """Q_x^h = 32 (the largest half-range order) and Q_y = Q_z = 8 (the largest
+    full-range orders), K = 4096: the projection tables no longer fit the
+    update block's LDS and are read from global memory; with body force the
+    force kernel spans 8 y-nodes.  140 cells: three update tiles."""
+    cfg = dict(I.config(flow, nx=140, qx_half=32, qy=8, qz=8), precision=prec)
+    s, o = _pair(cfg, 9)
+    s.step(4)
+    o.step(4)
+    if prec == 0:
+        _compare(s, o, TOL64, "%s K=4096" % flow)
+    else:
+        err = rel_moment_errors(s.moments(0), o.moments())
+        print("%s K=4096 FP32" % flow, {k: "%.1e" % v for k, v in err.items()}, flush=True)
+        for k in ("n", "uy", "T", "Pxy"):
+            assert err[k] < 1e-5, (k, err[k])
+        for k in ("ux", "qx"):
+            assert err[k] < 1e-4, (k, err[k])
