@@ -63,7 +63,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   A_LAT, A_INVDX, A_F64_0, A_F64_1, A_F64_2, A_TX64, A_TYZ64, A_IT64, A_GW64_0, A_GW64_1,
   A_F32_0, A_F32_1, A_F32_2, A_TX32, A_TYZ32, A_IT32, A_GW32_0, A_GW32_1,
-  A_PART, A_MOM, A_NW, A_FIELDS, A_COUNT
+  A_PART, A_MOM, A_FIELDS, A_COUNT
 };
 
 static void case_sizes(const CaseHost &c, size_t *sz) {
@@ -86,7 +86,6 @@ static void case_sizes(const CaseHost &c, size_t *sz) {
   }
   sz[A_PART] = nkx * NRAW * nx * 8;  // enough for one chunk per kx
   sz[A_MOM] = FDLB_NMOM * nx * 8;
-  sz[A_NW] = 2 * 8;
   sz[A_FIELDS] = 6 * nx * 8;
 }
 
@@ -360,7 +359,7 @@ extern "C" int fdlb_init(const fdlb_params *ps, int ncases, void *dev_ws, size_t
     d.gw[1][0] = arr[A_GW32_0]; d.gw[1][1] = arr[A_GW32_1];
     d.part = (double *)arr[A_PART];
     d.mom = (double *)arr[A_MOM];
-    d.nw = (double *)arr[A_NW];
+    d.nw[0] = d.nw[1] = 1.0;
     d.resid = h->d_resid + i;
     d.fields = (double *)arr[A_FIELDS];
     d.noise = (double *)arr[A_F64_1];   // f^(1) is free while a state is being set

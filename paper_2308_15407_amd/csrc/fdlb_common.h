@@ -26,6 +26,7 @@ __host__ __device__ inline int fslot(int cell) { return cell + cell / UTILE; }
 __host__ __device__ inline int fslots(int nx) { return 64 * ((nx + UTILE - 1) / UTILE); }
 
 // Offsets (in doubles) of the lattice constants of one case.
+// px, bP, bA, hQ, lam, ck, Hy, Hz are contiguous in that order.
 struct LatOff {
   int px, py, pz;   // node coordinates: [2qh], [qy], [qz]
   int kmat;         // momentum-derivative kernel [qy*qy] (App. A)
@@ -56,6 +57,9 @@ struct CaseDev {
   double eta0, kn, chi0, pr_fixed, ay, dt;
   double tau_pre;       // (5 sqrt(2 pi)/16) Kn chi0 ; 0 when Kn = infinity
   double wallD[2];      // sum over emitted nodes of p_x g^w (left, right)
+  double nw[2];         // wall densities of the current stage input, written by the table
+                        // pass's wall blocks; kept in the record so the update reads them
+                        // with the other fields
   double *lat;          // lattice constants
   LatOff lo;
   double *invdx;        // [nx] 1/(J_i deta)
@@ -66,7 +70,6 @@ struct CaseDev {
   void *gw[2][2];       // projected wall Maxwellians (n = 1) [K], per precision, per wall
   double *part;         // partial raw sums [nchunk][NRAW][nx]
   double *mom;          // [10][nx] moments of f^n (as of the last stage-1 table pass)
-  double *nw;           // [2] wall densities of the current stage input
   unsigned long long *resid;  // residual bits (max of non-negative doubles)
   double *fields;       // staging [6][nx] for set_state
   double *noise;        // staging [K][nx] for set_state (may be unused)

@@ -1,15 +1,16 @@
 // fdlb_kernels.hip -- gfx950 kernels of one FDLB stage (Sec. III.B).
 //
 // A stage is two launches over a flat block map that may span many cases:
-//   k_table  : per cell (32-cell tiles): moments of the stage input from the
+//   k_table  : per cell (16-cell tiles): moments of the stage input from the
 //              partial raw sums, closure (eq:chi, eq:viscosity, eq:tau,
 //              eq:prandtl), 6th-order gradients (Sec. III.B.3), the
 //              Shakhov/J1 polynomial (eq:j0, eq:j1) and its per-axis lattice
 //              projections (eq:hh_gk, eq:H_gk) written as tables n X_a[kx] and
 //              YZ_a[ky,kz]; two extra blocks per case reduce the incoming wall
 //              fluxes into the wall densities (impenetrability, Sec. III.B).
-//   k_update : per (63-cell tile, kx chunk): one 64-lane wave per y-line of
-//              velocities, lanes along cells (coalesced f[kappa][cell]); each
+//   k_update : per (63-cell tile, kx chunk): each wave takes a contiguous
+//              range of velocity rows (whole y-lines with body force), lanes
+//              along cells (coalesced f[kappa][cell]); each
 //              lane reconstructs one face by WENO-5 (eq:weno5_flux_x ..
 //              eq:weno5_sigma) and takes its right neighbour's face by a lane
 //              shuffle, adds the body force (eq:kernel_H) and the relaxation to
@@ -175,7 +176,7 @@ __device__ void wall_block(const CaseDev &c, int wall, int gin) {
   // Incoming populations reach the face through the fully interior third-order
   // candidate; emitted ones carry n_w g^w.
   __shared__ double red[256];
-  const T *g = (const T *)c.f[c.prec][gin];
+  const T *g = (const T *)c.f[sizeof(T) == 4 ? 1 : 0][gin];
   const int nx = c.nx, qh = c.qh, qyz = c.qyz;
   double acc = 0;
   const int n_in = qh * qyz;
@@ -197,7 +198,7 @@ __device__ void wall_block(const CaseDev &c, int wall, int gin) {
     if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) c.nw[wall] = (wall == 0 ? -red[0] : red[0]) / c.wallD[wall];
+  if (threadIdx.x == 0) const_cast<CaseDev &>(c).nw[wall] = (wall == 0 ? -red[0] : red[0]) / c.wallD[wall];
 }
 
 // full-range table values Y_b(p_k), b = 0..3, for one node from the Hermite
@@ -228,10 +229,10 @@ __device__ __forceinline__ void full_axis_values(double u, double T, int q, cons
 template <typename T>
 __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
                                                int mode, int gin) {
+  // launch maps list only active cases; padding entries have bm.x < 0
   const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[max(bm.x, 0)];
   if (bm.x < 0) return;
-  const CaseDev &c = cases[bm.x];
-  if (!c.active) return;
   if (bm.y < 0) {
     if (mode & TM_WALLS) wall_block<T>(c, -bm.y - 1, gin);
     return;
@@ -247,12 +248,12 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   constexpr int SCR = NSL * NRAW * W > CTILE * 2 * (NB + 1) ? NSL * NRAW * W : CTILE * 2 * (NB + 1);
   __shared__ double s_scr[SCR];
   double (*s_G)[2][NB + 1] = reinterpret_cast<double (*)[2][NB + 1]>(s_scr);
-  __shared__ double s_mb[CTILE][2][3];
   __shared__ double s_red[256];
-  __shared__ double s_lam[MAXQH * (NB + 1)];
-  __shared__ double s_b[4][NB];      // P_m, A_m, h_Q(P_m)
-  __shared__ double s_k[3][MAXQH];   // p_k, 1/h_Q'(p_k)
-  __shared__ double s_H[2][MAXQY * MAXQY];
+  // lattice constants, staged by one linear copy of their contiguous block
+  // [p_x (2 qh) | P_m | A_m | h_Q(P_m) | lambda (qh rows of NB) | c_k (qh) | H_y | H_z];
+  // the lambda rows are padded by one double in LDS (bank spread)
+  constexpr int NCST = 2 * MAXQH + 3 * NB + MAXQH * (NB + 1) + MAXQH + 2 * MAXQY * MAXQY;
+  __shared__ double s_cst[NCST];
   const int nx = c.nx, c0 = bm.y * CTILE;
   const int own = min(CTILE, nx - c0);
   const int tid = threadIdx.x;
@@ -260,30 +261,79 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   const LatOff lo = c.lo;
   const int qh = c.qh, qy = c.qy, qz = c.qz;
 
-  // ---- moments of the stage input for the tile and its halo ----
-  if (!(mode & TM_FIELDS)) {
-    // slice sl of cell w sums the chunks sl, sl + NSL, ...
-    const int w = tid % W, sl = tid / W, cell = c0 - CHALO + w;
-    if (sl < NSL) {
-      double S[NRAW];
+  // Every global read of the kernel is issued first so that the latencies
+  // overlap: the lattice constants (flat index over lambda, the base nodes,
+  // p_k / c_k, H_y, H_z), the chunk partials of the tile and its halo, and the
+  // metric and wall FD weights of the owned cells.  Three phases follow:
+  // moments; closure (first wave) beside the base weights (other waves); the
+  // X and YZ tables.
+  const GAS double *glat = gp<double>(lat);
+  constexpr int CB = 8;
+  static_assert(CB * 256 >= 3 * MAXQH + 3 * NB + MAXQH * NB + 2 * MAXQY * MAXQY, "constant staging");
+  const int cL0 = 2 * qh + 3 * NB, cL1 = cL0 + qh * NB, ncst = cL1 + qh + qy * qy + qz * qz;
+  double cv[CB];
+  if (mode & TM_TABLES) {
 #pragma unroll
-      for (int m = 0; m < NRAW; m++) S[m] = 0;
-      if (cell >= 0 && cell < nx) {
-        const int nch = c.nchunk;
-        for (int ch = sl; ch < nch; ch += NSL) {
-          const double *pp = c.part + (size_t)ch * NRAW * nx + cell;
-          double v[NRAW];
-#pragma unroll
-          for (int m = 0; m < NRAW; m++) v[m] = pp[(size_t)m * nx];
-#pragma unroll
-          for (int m = 0; m < NRAW; m++) S[m] += v[m];
-        }
-      }
-#pragma unroll
-      for (int m = 0; m < NRAW; m++) s_scr[(sl * NRAW + m) * W + w] = S[m];
+    for (int u = 0; u < CB; u++) {
+      const int it = tid + u * 256;
+      cv[u] = glat[lo.px + min(it, ncst - 1)];
     }
-    __syncthreads();
   }
+  const int ci = c0 + tid;
+  const double dxi_own = tid < own ? gp<double>(c.invdx)[min(ci, nx - 1)] : 0.0;
+  double fwv[7];
+  {
+    const bool wall_cell = tid < own && !(ci >= 3 && ci <= nx - 4);
+    const int r = wall_cell ? (ci < 3 ? ci : nx - 1 - ci) : 0;
+#pragma unroll
+    for (int jj = 0; jj < 7; jj++) fwv[jj] = wall_cell ? glat[lo.fdw + r * 7 + jj] : 0.0;
+  }
+  double bgs[NRAW];
+#pragma unroll
+  for (int m = 0; m < NRAW; m++) bgs[m] = sizeof(T) == 4 ? glat[lo.bgm + m] : 0.0;
+  // slice psl of cell pw sums the chunks psl, psl + NSL, ..., two per trip
+  const int pw = tid % W, psl = tid / W, pcell = c0 - CHALO + pw;
+  double S0[NRAW];
+#pragma unroll
+  for (int m = 0; m < NRAW; m++) S0[m] = 0;
+  if (!(mode & TM_FIELDS) && psl < NSL && pcell >= 0 && pcell < nx) {
+    const int nch = c.nchunk;
+    for (int ch = psl; ch < nch; ch += 2 * NSL) {
+      const bool two = ch + NSL < nch;
+      const GAS double *pa = gp<double>(c.part) + (size_t)ch * NRAW * nx + pcell;
+      const GAS double *pb = gp<double>(c.part) + (size_t)(two ? ch + NSL : ch) * NRAW * nx + pcell;
+      double va[NRAW], vb[NRAW];
+#pragma unroll
+      for (int m = 0; m < NRAW; m++) { va[m] = pa[(size_t)m * nx]; vb[m] = pb[(size_t)m * nx]; }
+#pragma unroll
+      for (int m = 0; m < NRAW; m++) {
+        S0[m] += va[m];
+        if (two) S0[m] += vb[m];
+      }
+    }
+  }
+  if (mode & TM_TABLES) {
+#pragma unroll
+    for (int u = 0; u < CB; u++) {
+      const int it = tid + u * 256;
+      if (it < ncst) {
+        const int q = it - cL0;
+        const int dst = it < cL0 ? it : (it < cL1 ? cL0 + (q / NB) * (NB + 1) + q % NB : it + qh);
+        s_cst[dst] = cv[u];
+      }
+    }
+  }
+  if (!(mode & TM_FIELDS) && psl < NSL) {
+#pragma unroll
+    for (int m = 0; m < NRAW; m++) s_scr[(psl * NRAW + m) * W + pw] = S0[m];
+  }
+  __syncthreads();
+
+  const double *s_px = s_cst, *s_P = s_cst + 2 * qh, *s_A = s_P + NB, *s_hQ = s_A + NB;
+  const double *s_lam = s_hQ + NB, *s_ck = s_lam + qh * (NB + 1);
+  const double *s_Hy = s_ck + qh, *s_Hz = s_Hy + qy * qy;
+
+  // ---- moments of the stage input for the tile and its halo ----
   double rmax = 0;
   if (tid < W) {
     const int cell = c0 - CHALO + tid;
@@ -304,7 +354,7 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
         if (sizeof(T) == 4) {
           // FP32 storage holds f - bg: add the background's raw sums
 #pragma unroll
-          for (int m = 0; m < NRAW; m++) S[m] += lat[lo.bgm + m];
+          for (int m = 0; m < NRAW; m++) S[m] += bgs[m];
         }
         n = S[0];
         ux = S[1] / n; uy = S[2] / n;
@@ -333,15 +383,6 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
         mo[7 * nx + cell] = pxy; mo[8 * nx + cell] = pyy; mo[9 * nx + cell] = pzz;
       }
     }
-  } else if (mode & TM_TABLES) {
-    // the other threads stage the lattice constants in LDS meanwhile
-    for (int it = tid - W; it < qh * NB; it += blockDim.x - W) s_lam[(it / NB) * (NB + 1) + it % NB] = lat[lo.lam + it];
-    for (int it = tid - W; it < NB; it += blockDim.x - W) {
-      s_b[0][it] = lat[lo.bP + it]; s_b[1][it] = lat[lo.bA + it]; s_b[2][it] = lat[lo.hQ + it];
-    }
-    for (int it = tid - W; it < qh; it += blockDim.x - W) { s_k[0][it] = lat[lo.px + it]; s_k[1][it] = lat[lo.ck + it]; }
-    for (int it = tid - W; it < qy * qy; it += blockDim.x - W) s_H[0][it] = lat[lo.Hy + it];
-    for (int it = tid - W; it < qz * qz; it += blockDim.x - W) s_H[1][it] = lat[lo.Hz + it];
   }
   if (mode & TM_RESID) {
     s_red[tid] = rmax;
@@ -379,7 +420,6 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
     } else {
       // gradients d/dx = (d/deta)/J, 6th-order central inside, one-sided at walls
       double g[5];
-      const double *fw = lat + lo.fdw;
 #pragma unroll
       for (int q = 0; q < 5; q++) {
         const double *src = q == 0 ? s_l[0] : (q == 1 ? s_l[1] : (q == 2 ? s_l[2] : (q == 3 ? s_m[1] : s_m[2])));
@@ -389,13 +429,13 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
               (src[li + 3] - src[li - 3]) * (1.0 / 60.0);
         } else if (i < 3) {
           d = 0;
-          for (int jj = 0; jj < 7; jj++) d += fw[i * 7 + jj] * src[li - i + jj];
+          for (int jj = 0; jj < 7; jj++) d += fwv[jj] * src[li - i + jj];
         } else {
           const int r = nx - 1 - i;
           d = 0;
-          for (int jj = 0; jj < 7; jj++) d -= fw[r * 7 + jj] * src[li + r - jj];
+          for (int jj = 0; jj < 7; jj++) d -= fwv[jj] * src[li + r - jj];
         }
-        g[q] = d * c.invdx[i];
+        g[q] = d * dxi_own;
       }
       const double eta = c.eta0 * n, chi = chi_cs(eta);
       const double brc = 4.0 * eta * chi;   // b rho chi
@@ -435,90 +475,81 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
     s_c[tid][0] = n; s_c[tid][1] = ux; s_c[tid][2] = uy; s_c[tid][3] = T_; s_c[tid][4] = itau;
 #pragma unroll
     for (int q = 0; q < 13; q++) s_c[tid][5 + q] = C[q];
-  }
-  __syncthreads();
-
-  // ---- half-range base weights per owned cell and half ----
-  for (int it = tid; it < own * 2 * NB; it += blockDim.x) {
-    const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
-    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1], T_ = s_c[cl][3];
-    const double d = s_b[0][m] - u;
-    s_G[cl][h][m] = exp(s_b[1][m] - d * d / (2.0 * T_)) * rsqrt(T_);
-  }
-  __syncthreads();
-  for (int it = tid; it < own * 2; it += blockDim.x) {
-    const int cl = it >> 1, h = it & 1;
-    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
-    double m0 = 0, m1 = 0, m2 = 0;
-#pragma unroll 8
-    for (int m = 0; m < NB; m++) {
-      const double d = s_b[0][m] - u, hv = s_b[2][m] * s_G[cl][h][m];
-      m0 += hv; m1 += hv * d; m2 += hv * d * d;
+  } else if (tid >= 64) {
+    // ---- half-range base weights per owned cell and half (waves 1..3) ----
+    static_assert(CTILE <= 64, "the closure runs on the first wave");
+    for (int it = tid - 64; it < own * 2 * NB; it += 256 - 64) {
+      const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
+      const double ux = s_m[1][cl + CHALO], T_ = s_m[3][cl + CHALO];
+      const double u = h == 0 ? ux : -ux;
+      const double d = s_P[m] - u;
+      s_G[cl][h][m] = exp(s_A[m] - d * d / (2.0 * T_)) * rsqrt(T_);
     }
-    s_mb[cl][h][0] = m0; s_mb[cl][h][1] = m1; s_mb[cl][h][2] = m2;
   }
   __syncthreads();
 
-  // ---- n X_a[kx] tables ----
-  // one item = one cell and half x a pair of nodes: each base weight read
-  // from LDS feeds two independent dot products
-  const int nkx = c.nkx;
-  T *tX = (T *)c.tabX[c.prec];
+  // ---- n X_a[kx] and YZ_a[ky,kz] tables, one flat item list ----
+  // an X item is one cell and half x a pair of nodes: each base weight read
+  // from LDS feeds the two dot products and the three base moments m_0..m_2
+  const int nkx = c.nkx, qyz = c.qyz;
+  constexpr int P = sizeof(T) == 4 ? 1 : 0;   // storage precision of this instantiation
+  T *tX = (T *)c.tabX[P];
+  T *tYZ = (T *)c.tabYZ[P];
   const int ngrp = (qh + 1) / 2;
-  for (int it = tid; it < own * 2 * ngrp; it += blockDim.x) {
-    const int cl = it % own, rest = it / own, h = rest & 1, k0 = 2 * (rest >> 1);   // cell fastest
-    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
-    const double *Gc = s_G[cl][h];
-    const double *l0 = s_lam + k0 * (NB + 1), *l1 = s_lam + min(k0 + 1, qh - 1) * (NB + 1);
-    double x[2] = {0.0, 0.0};
+  const int nXi = own * 2 * ngrp, nYi = own * qyz;
+  for (int it = tid; it < nXi + nYi; it += blockDim.x) {
+    if (it < nXi) {
+      const int cl = it % own, rest = it / own, h = rest & 1, k0 = 2 * (rest >> 1);   // cell fastest
+      const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
+      const double *Gc = s_G[cl][h];
+      const double *l0 = s_lam + k0 * (NB + 1), *l1 = s_lam + min(k0 + 1, qh - 1) * (NB + 1);
+      double x[2] = {0.0, 0.0}, mb[3] = {0.0, 0.0, 0.0};
 #pragma unroll 8
-    for (int m = 0; m < NB; m++) {
-      const double g = Gc[m];
-      x[0] += g * l0[m]; x[1] += g * l1[m];
-    }
-    const double *mb = s_mb[cl][h];
-    const double sg = h ? -1.0 : 1.0, n = s_c[cl][0];
-    const size_t i = (size_t)c0 + cl;
-#pragma unroll
-    for (int j = 0; j < 2; j++) {
-      const int k = k0 + j;
-      if (k < qh) {
-        const int kx = h * qh + k;
-        const double x0 = x[j], dk = s_k[0][k] - u, ck = s_k[1][k];
-        const double X1 = dk * x0 + ck * mb[0];
-        const double X2 = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
-        const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
-        tX[(size_t)(0 * nkx + kx) * nx + i] = (T)(n * x0);
-        tX[(size_t)(1 * nkx + kx) * nx + i] = (T)(n * sg * X1);
-        tX[(size_t)(2 * nkx + kx) * nx + i] = (T)(n * X2);
-        tX[(size_t)(3 * nkx + kx) * nx + i] = (T)(n * sg * X3);
+      for (int m = 0; m < NB; m++) {
+        const double g = Gc[m];
+        x[0] += g * l0[m]; x[1] += g * l1[m];
+        const double d = s_P[m] - u, hv = s_hQ[m] * g;
+        mb[0] += hv; mb[1] += hv * d; mb[2] += hv * d * d;
       }
+      const double sg = h ? -1.0 : 1.0, n = s_c[cl][0];
+      const size_t i = (size_t)c0 + cl;
+#pragma unroll
+      for (int j = 0; j < 2; j++) {
+        const int k = k0 + j;
+        if (k < qh) {
+          const int kx = h * qh + k;
+          const double x0 = x[j], dk = s_px[k] - u, ck = s_ck[k];
+          const double X1 = dk * x0 + ck * mb[0];
+          const double X2 = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
+          const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
+          tX[(size_t)(0 * nkx + kx) * nx + i] = (T)(n * x0);
+          tX[(size_t)(1 * nkx + kx) * nx + i] = (T)(n * sg * X1);
+          tX[(size_t)(2 * nkx + kx) * nx + i] = (T)(n * X2);
+          tX[(size_t)(3 * nkx + kx) * nx + i] = (T)(n * sg * X3);
+        }
+      }
+    } else {
+      const int iy = it - nXi;
+      const int cl = iy % own, yz = iy / own, ky = yz / qz, kz = yz % qz;
+      const double uy = s_c[cl][2], T_ = s_c[cl][3];
+      double Y[4], Z[4];
+      full_axis_values(uy, T_, qy, &s_Hy[ky * qy], Y);
+      full_axis_values(0.0, T_, qz, &s_Hz[kz * qz], Z);
+      const double *C = &s_c[cl][5];
+      const double Z0 = Z[0], Z2 = Z[2];
+      const double yz0 = C[0] * Y[0] * Z0 + C[2] * Y[1] * Z0 + C[4] * Y[2] * Z0 + C[11] * Y[3] * Z0 +
+                         C[5] * Y[0] * Z2 + C[12] * Y[1] * Z2;
+      const double yz1 = C[1] * Y[0] * Z0 + C[6] * Y[1] * Z0 + C[8] * Y[2] * Z0 + C[9] * Y[0] * Z2;
+      const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
+      const double yz3 = C[7] * Y[0] * Z0;
+      const size_t i = (size_t)c0 + cl;
+      tYZ[(size_t)(0 * qyz + yz) * nx + i] = (T)yz0;
+      tYZ[(size_t)(1 * qyz + yz) * nx + i] = (T)yz1;
+      tYZ[(size_t)(2 * qyz + yz) * nx + i] = (T)yz2;
+      tYZ[(size_t)(3 * qyz + yz) * nx + i] = (T)yz3;
     }
   }
-
-  // ---- YZ_a[ky,kz] tables and 1/tau ----
-  const int qyz = c.qyz;
-  T *tYZ = (T *)c.tabYZ[c.prec];
-  for (int it = tid; it < own * qyz; it += blockDim.x) {
-    const int cl = it % own, yz = it / own, ky = yz / qz, kz = yz % qz;
-    const double uy = s_c[cl][2], T_ = s_c[cl][3];
-    double Y[4], Z[4];
-    full_axis_values(uy, T_, qy, &s_H[0][ky * qy], Y);
-    full_axis_values(0.0, T_, qz, &s_H[1][kz * qz], Z);
-    const double *C = &s_c[cl][5];
-    const double Z0 = Z[0], Z2 = Z[2];
-    const double yz0 = C[0] * Y[0] * Z0 + C[2] * Y[1] * Z0 + C[4] * Y[2] * Z0 + C[11] * Y[3] * Z0 +
-                       C[5] * Y[0] * Z2 + C[12] * Y[1] * Z2;
-    const double yz1 = C[1] * Y[0] * Z0 + C[6] * Y[1] * Z0 + C[8] * Y[2] * Z0 + C[9] * Y[0] * Z2;
-    const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
-    const double yz3 = C[7] * Y[0] * Z0;
-    const size_t i = (size_t)c0 + cl;
-    tYZ[(size_t)(0 * qyz + yz) * nx + i] = (T)yz0;
-    tYZ[(size_t)(1 * qyz + yz) * nx + i] = (T)yz1;
-    tYZ[(size_t)(2 * qyz + yz) * nx + i] = (T)yz2;
-    tYZ[(size_t)(3 * qyz + yz) * nx + i] = (T)yz3;
-  }
-  if (tid < own) ((T *)c.invtau[c.prec])[c0 + tid] = (T)s_c[tid][4];
+  if (tid < own) ((T *)c.invtau[P])[c0 + tid] = (T)s_c[tid][4];
 }
 
 // ---------------------------------------------------------------------------
@@ -567,15 +598,15 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
   extern __shared__ double lds_dyn[];
   // FP32 storage holds the deviation from the case's background populations
   constexpr bool DF = sizeof(T) == 4;
+  // launch maps list only active cases; padding entries have bm.x < 0
   const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[max(bm.x, 0)];
   if (bm.x < 0) return;
-  const CaseDev &c = cases[bm.x];
-  if (!c.active) return;
   // the wave index is uniform within a wave: keep it (and everything derived
   // from it -- rows, pointers, loop bounds) in scalar registers
   const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), nwv = blockDim.x >> 6;
   const int nx = c.nx, qy = c.qy, qz = c.qz, qyz = c.qyz, nkx = c.nkx;
-  const int P = c.prec;
+  constexpr int P = sizeof(T) == 4 ? 1 : 0;   // storage precision of this instantiation
   const GAS T *__restrict__ gin = gp<T>(c.f[P][STAGE == 1 ? 0 : (STAGE == 2 ? 1 : 2)]);
   // stage 3 writes f^{n+1} over f^n: each lane reads f^n only at the node it writes
   const GAS T *fn = gp<T>(c.f[P][0]);
@@ -595,13 +626,19 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
   const unsigned bcf = (unsigned)fslot(jc) * (unsigned)sizeof(T);
   const unsigned bw = (unsigned)fslot(max(j, 0)) * (unsigned)sizeof(T);
   const int kx0 = bm.z * c.kxc, kx1 = min(kx0 + c.kxc, nkx);
-  const double nwl = gp<double>(c.nw)[0], nwr = gp<double>(c.nw)[1];
-  const T dxi = (T)gp<double>(c.invdx)[jc];
-  const T itau = gp<T>(c.invtau[P])[jc];
-  (void)itau;
+  const double nwl = c.nw[0], nwr = c.nw[1];
+  // 1/dx and 1/tau of the lane's cell: without body force they are loaded
+  // after the table staging, so that no load is outstanding when the staging
+  // loop starts
+  T dxi = 0, itau = 0;
+  const GAS double *__restrict__ invdx = gp<double>(c.invdx);
+  const GAS T *__restrict__ invtau = gp<T>(c.invtau[P]);
+  if (FORCE) { dxi = (T)invdx[jc]; itau = invtau[jc]; }
   const T dt = (T)c.dt;
   const size_t tstride = (size_t)nx;             // row stride of the [.][cell] tables
   const size_t fstride = (size_t)c.nxp;          // row stride of the population arrays (slots)
+  const int c_qh = c.qh, c_kxc = c.kxc, c_tlds = c.tlds;
+  const int lo_px = c.lo.px, lo_py = c.lo.py, lo_pz = c.lo.pz, lo_phi = c.lo.phi, lo_bg = c.lo.bg;
   // clamped stencil offsets for both upwind directions and ghost flags
   unsigned op0, op1, op2, op3, op4, on0, on1, on2, on3, on4;
   bool gp0, gp1, gp2, gn2, gn3, gn4;
@@ -630,7 +667,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     }
     if (is_cell) stb(out + (size_t)kap * fstride, bw, o);
     {
-      const double pyd = lat[c.lo.py + ky], pzd = lat[c.lo.pz + kz];
+      const double pyd = lat[lo_py + ky], pzd = lat[lo_pz + kz];
       const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
       const double od = is_cell ? (double)o : 0.0;
       acc[0] += od;
@@ -675,37 +712,62 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     const int nrows = (kx1 - kx0) * qyz;
     const int per = (nrows + nwv - 1) / nwv;
     const int r0 = min(wv * per, nrows), r1 = min(r0 + per, nrows);
-    const int rsplit = min(max((c.qh - kx0) * qyz, 0), nrows);
+    const int rsplit = min(max((c_qh - kx0) * qyz, 0), nrows);
     const int kap_base = kx0 * qyz;
-    const bool tlds = c.tlds != 0;
+    const bool tlds = c_tlds != 0;
     // LDS tables of the tile, four coefficients a = 0..3 adjacent per lane:
     // sYZ[(yz * 64 + lane) * 4 + a], sX[(kl * 64 + lane) * 4 + a]
     T *sYZ = (T *)lds_dyn, *sX = sYZ + 4 * qyz * 64;
     if (tlds) {
-      const int jcl = min(c0 + lane, nx - 1);
-      for (int rr = wv; rr < 4 * qyz; rr += nwv) {
-        const int a = rr / qyz, yz = rr - a * qyz;
-        sYZ[(yz * 64 + lane) * 4 + a] = tYZ[((size_t)a * qyz + yz) * tstride + jcl];
-      }
-      const int nk = kx1 - kx0;
-      for (int rr = wv; rr < 4 * nk; rr += nwv) {
-        const int a = rr / nk, k = rr - a * nk;
-        sX[(k * 64 + lane) * 4 + a] = tX[((size_t)a * nkx + kx0 + k) * tstride + jcl];
+      // table rows 0 .. 4 qyz - 1 are YZ_a[yz], the rest X_a[kx]; each wave
+      // issues SB row loads (clamped to a valid row) before it writes any of
+      // them to LDS, so their latencies overlap
+      constexpr int SB = 8;
+      const unsigned bj = (unsigned)min(c0 + lane, nx - 1) * (unsigned)sizeof(T);
+      const int nk = kx1 - kx0, nyz = 4 * qyz, nr = nyz + 4 * nk;
+      for (int base = wv; base < nr; base += SB * nwv) {
+        T v[SB];
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+          const int rr = min(base + u * nwv, nr - 1);
+          const GAS T *src;
+          if (rr < nyz) {
+            const int a = rr / qyz, yz = rr - a * qyz;
+            src = tYZ + ((size_t)a * qyz + yz) * tstride;
+          } else {
+            const int q = rr - nyz, a = q / nk, k = q - a * nk;
+            src = tX + ((size_t)a * nkx + kx0 + k) * tstride;
+          }
+          v[u] = ldb(src, bj);
+        }
+#pragma unroll
+        for (int u = 0; u < SB; u++) {
+          const int rr = base + u * nwv;
+          if (rr < nyz) {
+            const int a = rr / qyz, yz = rr - a * qyz;
+            sYZ[(yz * 64 + lane) * 4 + a] = v[u];
+          } else if (rr < nr) {
+            const int q = rr - nyz, a = q / nk, k = q - a * nk;
+            sX[(k * 64 + lane) * 4 + a] = v[u];
+          }
+        }
       }
       __syncthreads();
     }
+    dxi = (T)invdx[jc];
+    itau = invtau[jc];
     const bool interior = tlds && c0 >= 3 && c0 + 66 <= nx;
     // interior tiles: per-wave LDS row buffers after the tables.  The row load
     // takes the tile's 64 aligned slots (cells c0 .. c0+62 and the padding
     // slot); a second load brings the halo: cells c0-3 .. c0-1 on lanes 0..2
     // and c0+63 .. c0+65 on lanes 3..5 (other lanes read past the row: zero)
-    T *sRow = sX + 4 * c.kxc * 64 + wv * 2 * ROWBUF;
+    T *sRow = sX + 4 * c_kxc * 64 + wv * 2 * ROWBUF;
     const unsigned oa = (unsigned)(64 * bm.y + lane) * (unsigned)sizeof(T);
     const unsigned oh = lane < 3 ? (unsigned)fslot(max(c0 - 3 + lane, 0)) * (unsigned)sizeof(T)
                                  : (lane < 6 ? (unsigned)fslot(min(c0 + 60 + lane, nx - 1)) * (unsigned)sizeof(T)
                                              : 0x80000000u);
-    const CAS double *__restrict__ phi = (const CAS double *)(c.lat + c.lo.phi);
-    const CAS double *__restrict__ bgc = (const CAS double *)(c.lat + c.lo.bg);
+    const CAS double *__restrict__ phi = (const CAS double *)(c.lat + lo_phi);
+    const CAS double *__restrict__ bgc = (const CAS double *)(c.lat + lo_bg);
     typedef T T4 __attribute__((ext_vector_type(4)));
     const unsigned rowbytes = (unsigned)c.nxp * (unsigned)sizeof(T);
     // global loads of a row (stencil of the stage input and f^n) are issued
@@ -846,8 +908,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     const int nlines = (kx1 - kx0) * qz;
     for (int line = wv; line < nlines; line += nwv) {
       const int kx = kx0 + line / qz, kz = line - (line / qz) * qz;
-      const double pxd = lat[c.lo.px + kx];
-      const bool pos = kx < c.qh;               // positive x nodes come first
+      const double pxd = lat[lo_px + kx];
+      const bool pos = kx < c_qh;               // positive x nodes come first
       const size_t xa = (size_t)nkx * tstride;
       const GAS T *xr = tX + (size_t)kx * tstride;
       const T X0 = ldb(xr, bc), X1 = ldb(xr + xa, bc), X2 = ldb(xr + 2 * xa, bc), X3 = ldb(xr + 3 * xa, bc);
@@ -893,7 +955,8 @@ __global__ void __launch_bounds__(512) k_fill(const CaseDev *__restrict__ cases,
   const CaseDev &c = cases[bm.x];
   if (!c.active) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-  const int nx = c.nx, qy = c.qy, qz = c.qz, qyz = c.qyz, nkx = c.nkx, P = c.prec;
+  const int nx = c.nx, qy = c.qy, qz = c.qz, qyz = c.qyz, nkx = c.nkx;
+  constexpr int P = sizeof(T) == 4 ? 1 : 0;
   T *f = (T *)c.f[P][0];
   const T *tX = (const T *)c.tabX[P];
   const T *tYZ = (const T *)c.tabYZ[P];
@@ -936,7 +999,8 @@ __global__ void __launch_bounds__(512) k_partials(const CaseDev *__restrict__ ca
   const CaseDev &c = cases[bm.x];
   if (!c.active) return;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6, nwv = blockDim.x >> 6;
-  const int nx = c.nx, qz = c.qz, qyz = c.qyz, nkx = c.nkx, P = c.prec;
+  const int nx = c.nx, qz = c.qz, qyz = c.qyz, nkx = c.nkx;
+  constexpr int P = sizeof(T) == 4 ? 1 : 0;
   const T *f = (const T *)c.f[P][0];
   const double *lat = c.lat;
   const int c0 = bm.y * UTILE, j = c0 + lane;

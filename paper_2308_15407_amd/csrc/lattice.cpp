@@ -192,17 +192,19 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   // lattice offsets
   LatOff &o = c.lo;
   int off = 0;
+  // p_x .. H_z form one contiguous block in this order (the table kernel
+  // stages it with a single linear copy)
   o.px = off; off += 2 * Q;
-  o.py = off; off += c.qy;
-  o.pz = off; off += c.qz;
-  o.kmat = off; off += c.qy * c.qy;
   o.bP = off; off += NB;
   o.bA = off; off += NB;
-  o.lam = off; off += Q * NB;
   o.hQ = off; off += NB;
+  o.lam = off; off += Q * NB;
   o.ck = off; off += Q;
   o.Hy = off; off += c.qy * c.qy;
   o.Hz = off; off += c.qz * c.qz;
+  o.py = off; off += c.qy;
+  o.pz = off; off += c.qz;
+  o.kmat = off; off += c.qy * c.qy;
   o.fdw = off; off += 3 * 7;
   off = (off + 7) & ~7;   // 64-byte aligned rows (one scalar load per velocity)
   o.phi = off; off += c.K * 8;
