@@ -16,6 +16,10 @@ constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
 #endif
 constexpr int CTILE = FDLB_CTILE;  // cells per table block
 constexpr int CHALO = 6;       // moment halo of a table block
+#ifndef FDLB_TABLE_WIDE_MAX
+#define FDLB_TABLE_WIDE_MAX 128
+#endif
+constexpr int TABLE_WIDE_MAX = FDLB_TABLE_WIDE_MAX;  // table maps up to this many blocks use 512 threads
 constexpr int NRAW = 9;        // raw moment sums per cell
 constexpr int ROWBUF = 72;     // LDS row buffer of an interior update tile (69 cells, padded); two per wave
 

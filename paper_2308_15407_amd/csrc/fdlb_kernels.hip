@@ -170,12 +170,12 @@ __device__ __forceinline__ double chi_cs(double eta) {
 // ---------------------------------------------------------------------------
 // table pass
 // ---------------------------------------------------------------------------
-template <typename T>
+template <typename T, int NT>
 __device__ void wall_block(const CaseDev &c, int wall, int gin) {
   // impenetrability: the numerical mass flux through the wall face vanishes.
   // Incoming populations reach the face through the fully interior third-order
   // candidate; emitted ones carry n_w g^w.
-  __shared__ double red[256];
+  __shared__ double red[NT];
   const T *g = (const T *)c.f[sizeof(T) == 4 ? 1 : 0][gin];
   const int nx = c.nx, qh = c.qh, qyz = c.qyz;
   double acc = 0;
@@ -226,15 +226,15 @@ __device__ __forceinline__ void full_axis_values(double u, double T, int q, cons
     }
 }
 
-template <typename T>
-__global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
+template <typename T, int NT>
+__global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
                                                int mode, int gin) {
   // launch maps list only active cases; padding entries have bm.x < 0
   const int4 bm = map[blockIdx.x];
   const CaseDev &c = cases[max(bm.x, 0)];
   if (bm.x < 0) return;
   if (bm.y < 0) {
-    if (mode & TM_WALLS) wall_block<T>(c, -bm.y - 1, gin);
+    if (mode & TM_WALLS) wall_block<T, NT>(c, -bm.y - 1, gin);
     return;
   }
   constexpr int W = CTILE + 2 * CHALO;
@@ -244,11 +244,11 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   // the chunk partials are summed by all threads in NSL slices first; the
   // same LDS later holds the base weights G (rows padded by one double so
   // that lanes reading different cells or nodes fall in different banks)
-  constexpr int NSL = 256 / W;
+  constexpr int NSL = 256 / W;      // partial-sum slices (the first 256 threads)
   constexpr int SCR = NSL * NRAW * W > CTILE * 2 * (NB + 1) ? NSL * NRAW * W : CTILE * 2 * (NB + 1);
   __shared__ double s_scr[SCR];
   double (*s_G)[2][NB + 1] = reinterpret_cast<double (*)[2][NB + 1]>(s_scr);
-  __shared__ double s_red[256];
+  __shared__ double s_red[NT];
   // lattice constants, staged by one linear copy of their contiguous block
   // [p_x (2 qh) | P_m | A_m | h_Q(P_m) | lambda (qh rows of NB) | c_k (qh) | H_y | H_z];
   // the lambda rows are padded by one double in LDS (bank spread)
@@ -268,14 +268,14 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   // moments; closure (first wave) beside the base weights (other waves); the
   // X and YZ tables.
   const GAS double *glat = gp<double>(lat);
-  constexpr int CB = 8;
-  static_assert(CB * 256 >= 3 * MAXQH + 3 * NB + MAXQH * NB + 2 * MAXQY * MAXQY, "constant staging");
+  constexpr int CB = 2048 / NT;
+  static_assert(CB * NT >= 3 * MAXQH + 3 * NB + MAXQH * NB + 2 * MAXQY * MAXQY, "constant staging");
   const int cL0 = 2 * qh + 3 * NB, cL1 = cL0 + qh * NB, ncst = cL1 + qh + qy * qy + qz * qz;
   double cv[CB];
   if (mode & TM_TABLES) {
 #pragma unroll
     for (int u = 0; u < CB; u++) {
-      const int it = tid + u * 256;
+      const int it = tid + u * NT;
       cv[u] = glat[lo.px + min(it, ncst - 1)];
     }
   }
@@ -315,7 +315,7 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   if (mode & TM_TABLES) {
 #pragma unroll
     for (int u = 0; u < CB; u++) {
-      const int it = tid + u * 256;
+      const int it = tid + u * NT;
       if (it < ncst) {
         const int q = it - cL0;
         const int dst = it < cL0 ? it : (it < cL1 ? cL0 + (q / NB) * (NB + 1) + q % NB : it + qh);
@@ -387,7 +387,7 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   if (mode & TM_RESID) {
     s_red[tid] = rmax;
     __syncthreads();
-    for (int s = 128; s > 0; s >>= 1) {
+    for (int s = NT / 2; s > 0; s >>= 1) {
       if (tid < s) {
         const double a = s_red[tid], b = s_red[tid + s];
         s_red[tid] = (a != a || b != b) ? __longlong_as_double(0x7ff8000000000000LL) : fmax(a, b);
@@ -478,7 +478,7 @@ __global__ void __launch_bounds__(256) k_table(const CaseDev *__restrict__ cases
   } else if (tid >= 64) {
     // ---- half-range base weights per owned cell and half (waves 1..3) ----
     static_assert(CTILE <= 64, "the closure runs on the first wave");
-    for (int it = tid - 64; it < own * 2 * NB; it += 256 - 64) {
+    for (int it = tid - 64; it < own * 2 * NB; it += NT - 64) {
       const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
       const double ux = s_m[1][cl + CHALO], T_ = s_m[3][cl + CHALO];
       const double u = h == 0 ? ux : -ux;
@@ -1073,8 +1073,15 @@ hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblo
                         hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
   const int4 *m = (const int4 *)map;
-  if (prec == 0) launch_k(k_table<double>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
-  else launch_k(k_table<float>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
+  // small maps are latency-bound: twice the threads per block shorten the
+  // per-phase work of each thread; large maps keep more blocks resident
+  if (nblocks <= TABLE_WIDE_MAX) {
+    if (prec == 0) launch_k(k_table<double, 512>, dim3(nblocks), dim3(512), 0, s, e0, e1, cases, m, mode, gin);
+    else launch_k(k_table<float, 512>, dim3(nblocks), dim3(512), 0, s, e0, e1, cases, m, mode, gin);
+  } else {
+    if (prec == 0) launch_k(k_table<double, 256>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
+    else launch_k(k_table<float, 256>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
+  }
   return hipGetLastError();
 }
 
