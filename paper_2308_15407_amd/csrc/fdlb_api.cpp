@@ -191,7 +191,11 @@ static int build_maps(fdlb_ctx *h) {
     const bool force = c.p.ay != 0.0;
     const int qyz = c.qy * c.qz;
     // update blocks of force-free cases stage their tables in LDS when they fit
-    d.tlds = (!force && update_lds_bytes(c.prec, qyz, c.kxc, h->waves, true) <= UPDATE_LDS_MAX) ? 1 : 0;
+    // and each wave has enough velocity rows to repay the staging (with only a
+    // few rows per wave, reading the table values per row is faster)
+    const int rows_per_wave = (c.kxc * qyz + h->waves - 1) / h->waves;
+    d.tlds = (!force && rows_per_wave >= TLDS_MIN_ROWS &&
+              update_lds_bytes(c.prec, qyz, c.kxc, h->waves, true) <= UPDATE_LDS_MAX) ? 1 : 0;
     if (!c.active) continue;
     const int P = c.prec * 2 + (force ? 1 : 0);
     h->lds[P] = std::max(h->lds[P], update_lds_bytes(c.prec, qyz, c.kxc, h->waves, d.tlds != 0));

@@ -48,6 +48,11 @@ hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblo
 // dynamic LDS of an update launch: partial sums of the waves, or the staged
 // projection tables of a tile when tlds (at most UPDATE_LDS_MAX bytes)
 constexpr size_t UPDATE_LDS_MAX = 65536;
+// fewest velocity rows per wave for which an update block stages its tables in LDS
+#ifndef FDLB_TLDS_MIN_ROWS
+#define FDLB_TLDS_MIN_ROWS 8
+#endif
+constexpr int TLDS_MIN_ROWS = FDLB_TLDS_MIN_ROWS;
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds);
 hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
                          int force, size_t lds, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
