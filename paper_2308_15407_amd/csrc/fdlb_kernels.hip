@@ -245,6 +245,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   // same LDS later holds the base weights G (rows padded by one double so
   // that lanes reading different cells or nodes fall in different banks)
   constexpr int NSL = 256 / W;      // partial-sum slices (the first 256 threads)
+  static_assert(NRAW * W <= 256, "one thread per raw moment and cell of the tile and halo");
   constexpr int SCR = NSL * NRAW * W > CTILE * 2 * (NB + 1) ? NSL * NRAW * W : CTILE * 2 * (NB + 1);
   __shared__ double s_scr[SCR];
   double (*s_G)[2][NB + 1] = reinterpret_cast<double (*)[2][NB + 1]>(s_scr);
@@ -328,6 +329,17 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
     for (int m = 0; m < NRAW; m++) s_scr[(psl * NRAW + m) * W + pw] = S0[m];
   }
   __syncthreads();
+  if (!(mode & TM_FIELDS)) {
+    // one thread per (raw moment, cell) adds the slices, in slice order, into
+    // slice 0's entry (no other thread touches that entry)
+    if (tid < NRAW * W) {
+      const int m = tid / W, w = tid - m * W;
+      double a = 0;
+      for (int sl = 0; sl < NSL; sl++) a += s_scr[(sl * NRAW + m) * W + w];
+      s_scr[m * W + w] = a;
+    }
+    __syncthreads();
+  }
 
   const double *s_px = s_cst, *s_P = s_cst + 2 * qh, *s_A = s_P + NB, *s_hQ = s_A + NB;
   const double *s_lam = s_hQ + NB, *s_ck = s_lam + qh * (NB + 1);
@@ -346,11 +358,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
       } else {
         double S[NRAW];
 #pragma unroll
-        for (int m = 0; m < NRAW; m++) {
-          double a = 0;
-          for (int sl = 0; sl < NSL; sl++) a += s_scr[(sl * NRAW + m) * W + tid];
-          S[m] = a;
-        }
+        for (int m = 0; m < NRAW; m++) S[m] = s_scr[m * W + tid];
         if (sizeof(T) == 4) {
           // FP32 storage holds f - bg: add the background's raw sums
 #pragma unroll
