@@ -241,12 +241,11 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy
   __shared__ double s_l[3][W];      // ln n, ln chi, ln T
   __shared__ double s_c[CTILE][20]; // n, ux, uy, T, invtau, C[13]
-  // the chunk partials are summed by all threads in NSL slices first; the
-  // same LDS later holds the base weights G (rows padded by one double so
-  // that lanes reading different cells or nodes fall in different banks)
-  constexpr int NSL = 256 / W;      // partial-sum slices (the first 256 threads)
+  // the raw sums of the tile and its halo first, then the base weights G
+  // (rows padded by one double so that lanes reading different cells or
+  // nodes fall in different banks)
   static_assert(NRAW * W <= 256, "one thread per raw moment and cell of the tile and halo");
-  constexpr int SCR = NSL * NRAW * W > CTILE * 2 * (NB + 1) ? NSL * NRAW * W : CTILE * 2 * (NB + 1);
+  constexpr int SCR = NRAW * W > CTILE * 2 * (NB + 1) ? NRAW * W : CTILE * 2 * (NB + 1);
   __shared__ double s_scr[SCR];
   double (*s_G)[2][NB + 1] = reinterpret_cast<double (*)[2][NB + 1]>(s_scr);
   __shared__ double s_red[NT];
@@ -292,25 +291,24 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   double bgs[NRAW];
 #pragma unroll
   for (int m = 0; m < NRAW; m++) bgs[m] = sizeof(T) == 4 ? glat[lo.bgm + m] : 0.0;
-  // slice psl of cell pw sums the chunks psl, psl + NSL, ..., two per trip
-  const int pw = tid % W, psl = tid / W, pcell = c0 - CHALO + pw;
-  double S0[NRAW];
-#pragma unroll
-  for (int m = 0; m < NRAW; m++) S0[m] = 0;
-  if (!(mode & TM_FIELDS) && psl < NSL && pcell >= 0 && pcell < nx) {
+  // one thread per (raw moment, cell of the tile and halo) adds the chunk
+  // partials in chunk order; up to PB chunk loads are in flight at a time
+  // (the chunk count is uniform, so the guards are scalar branches)
+  constexpr int PB = 16;
+  const int pm = tid / W, pw = tid - pm * W, pcell = c0 - CHALO + pw;
+  double praw = 0.0;
+  if (!(mode & TM_FIELDS) && tid < NRAW * W && pcell >= 0 && pcell < nx) {
     const int nch = c.nchunk;
-    for (int ch = psl; ch < nch; ch += 2 * NSL) {
-      const bool two = ch + NSL < nch;
-      const GAS double *pa = gp<double>(c.part) + (size_t)ch * NRAW * nx + pcell;
-      const GAS double *pb = gp<double>(c.part) + (size_t)(two ? ch + NSL : ch) * NRAW * nx + pcell;
-      double va[NRAW], vb[NRAW];
+    const GAS double *pp = gp<double>(c.part) + (size_t)pm * nx + pcell;
+    const size_t cstride = (size_t)NRAW * nx;
+    for (int ch0 = 0; ch0 < nch; ch0 += PB) {
+      double v[PB];
 #pragma unroll
-      for (int m = 0; m < NRAW; m++) { va[m] = pa[(size_t)m * nx]; vb[m] = pb[(size_t)m * nx]; }
+      for (int k = 0; k < PB; k++)
+        if (ch0 + k < nch) v[k] = pp[(size_t)(ch0 + k) * cstride];
 #pragma unroll
-      for (int m = 0; m < NRAW; m++) {
-        S0[m] += va[m];
-        if (two) S0[m] += vb[m];
-      }
+      for (int k = 0; k < PB; k++)
+        if (ch0 + k < nch) praw += v[k];
     }
   }
   if (mode & TM_TABLES) {
@@ -324,22 +322,8 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
       }
     }
   }
-  if (!(mode & TM_FIELDS) && psl < NSL) {
-#pragma unroll
-    for (int m = 0; m < NRAW; m++) s_scr[(psl * NRAW + m) * W + pw] = S0[m];
-  }
+  if (!(mode & TM_FIELDS) && tid < NRAW * W) s_scr[pm * W + pw] = praw;
   __syncthreads();
-  if (!(mode & TM_FIELDS)) {
-    // one thread per (raw moment, cell) adds the slices, in slice order, into
-    // slice 0's entry (no other thread touches that entry)
-    if (tid < NRAW * W) {
-      const int m = tid / W, w = tid - m * W;
-      double a = 0;
-      for (int sl = 0; sl < NSL; sl++) a += s_scr[(sl * NRAW + m) * W + w];
-      s_scr[m * W + w] = a;
-    }
-    __syncthreads();
-  }
 
   const double *s_px = s_cst, *s_P = s_cst + 2 * qh, *s_A = s_P + NB, *s_hQ = s_A + NB;
   const double *s_lam = s_hQ + NB, *s_ck = s_lam + qh * (NB + 1);
