@@ -170,35 +170,41 @@ __device__ __forceinline__ double chi_cs(double eta) {
 // ---------------------------------------------------------------------------
 // table pass
 // ---------------------------------------------------------------------------
-template <typename T, int NT>
+// Wall density n_w of one wall from the stage input g (impenetrability: the
+// numerical mass flux through the wall face vanishes).  Incoming populations
+// reach the face through the fully interior third-order candidate; emitted
+// ones carry n_w g^w.  The first 256 threads of the block take part, with the
+// same summation order for any block width, so 256- and 512-thread table
+// blocks give the same bits.
+template <typename T>
 __device__ void wall_block(const CaseDev &c, int wall, int gin) {
-  // impenetrability: the numerical mass flux through the wall face vanishes.
-  // Incoming populations reach the face through the fully interior third-order
-  // candidate; emitted ones carry n_w g^w.
-  __shared__ double red[NT];
+  __shared__ double red[256];
   const T *g = (const T *)c.f[sizeof(T) == 4 ? 1 : 0][gin];
   const int nx = c.nx, qh = c.qh, qyz = c.qyz;
+  const int tid = threadIdx.x;
   double acc = 0;
   const int n_in = qh * qyz;
-  for (int t = threadIdx.x; t < n_in; t += blockDim.x) {
-    const int kx = (wall == 0 ? qh : 0) + t / qyz;
-    const int kap = kx * qyz + t % qyz;
-    const double p = c.lat[c.lo.px + kx];
-    const T *row = g + (size_t)kap * c.nxp;
-    double f0, f1, f2;
-    if (wall == 0) { f0 = row[fslot(0)]; f1 = row[fslot(1)]; f2 = row[fslot(2)]; }
-    else { f0 = row[fslot(nx - 1)]; f1 = row[fslot(nx - 2)]; f2 = row[fslot(nx - 3)]; }
-    // the extrapolation weights sum to one: the background passes through
-    const double bgk = sizeof(T) == 4 ? c.lat[c.lo.bg + kap] : 0.0;
-    acc += p * (bgk + (f2 * (1.0 / 3.0) - f1 * (7.0 / 6.0) + f0 * (11.0 / 6.0)));
+  if (tid < 256) {
+    for (int t = tid; t < n_in; t += 256) {
+      const int kx = (wall == 0 ? qh : 0) + t / qyz;
+      const int kap = kx * qyz + t % qyz;
+      const double p = c.lat[c.lo.px + kx];
+      const T *row = g + (size_t)kap * c.nxp;
+      double f0, f1, f2;
+      if (wall == 0) { f0 = row[fslot(0)]; f1 = row[fslot(1)]; f2 = row[fslot(2)]; }
+      else { f0 = row[fslot(nx - 1)]; f1 = row[fslot(nx - 2)]; f2 = row[fslot(nx - 3)]; }
+      // the extrapolation weights sum to one: the background passes through
+      const double bgk = sizeof(T) == 4 ? c.lat[c.lo.bg + kap] : 0.0;
+      acc += p * (bgk + (f2 * (1.0 / 3.0) - f1 * (7.0 / 6.0) + f0 * (11.0 / 6.0)));
+    }
+    red[tid] = acc;
   }
-  red[threadIdx.x] = acc;
   __syncthreads();
-  for (int s = blockDim.x / 2; s > 0; s >>= 1) {
-    if ((int)threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+  for (int s = 128; s > 0; s >>= 1) {
+    if (tid < s) red[tid] += red[tid + s];
     __syncthreads();
   }
-  if (threadIdx.x == 0) const_cast<CaseDev &>(c).nw[wall] = (wall == 0 ? -red[0] : red[0]) / c.wallD[wall];
+  if (tid == 0) const_cast<CaseDev &>(c).nw[wall] = (wall == 0 ? -red[0] : red[0]) / c.wallD[wall];
 }
 
 // full-range table values Y_b(p_k), b = 0..3, for one node from the Hermite
@@ -234,7 +240,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   const CaseDev &c = cases[max(bm.x, 0)];
   if (bm.x < 0) return;
   if (bm.y < 0) {
-    if (mode & TM_WALLS) wall_block<T, NT>(c, -bm.y - 1, gin);
+    if (mode & TM_WALLS) wall_block<T>(c, -bm.y - 1, gin);
     return;
   }
   constexpr int W = CTILE + 2 * CHALO;
