@@ -52,6 +52,11 @@ struct fdlb_ctx {
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
   hipStream_t cap_stream = nullptr;
+  // with several launch groups, every group after the first runs its steps on
+  // a stream of its own (default priority), forked from and joined to the
+  // caller's stream by events; created by build_maps, never while capturing
+  hipStream_t gstream[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t fork_ev = nullptr, join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int converge_hist = 20;
   bool restart_nonfinite = false;   // run_to_steady: restart a diverged case once from its cold state
   std::vector<long> restarts;       // restarts per case in the last run_to_steady
@@ -223,6 +228,15 @@ static int build_maps(fdlb_ctx *h) {
       HIPCHK(hipMemcpyAsync(h->d_mapU[P], mu[P].data(), mu[P].size() * 4, hipMemcpyHostToDevice, h->stream));
     off += mu[P].size() / 4;
   }
+  int ng = 0;
+  for (int G = 0; G < 4; G++) ng += h->nU[G] > 0;
+  if (ng > 1) {
+    if (!h->fork_ev) HIPCHK(hipEventCreateWithFlags(&h->fork_ev, hipEventDisableTiming));
+    for (int G = 1; G < 4; G++) {
+      if (!h->gstream[G]) HIPCHK(hipStreamCreateWithFlags(&h->gstream[G], hipStreamNonBlocking));
+      if (!h->join_ev[G]) HIPCHK(hipEventCreateWithFlags(&h->join_ev[G], hipEventDisableTiming));
+    }
+  }
   int r = upload_cases(h);
   if (r) return r;
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -232,15 +246,42 @@ static int build_maps(fdlb_ctx *h) {
 // ---------------------------------------------------------------------------
 // stage launches
 // ---------------------------------------------------------------------------
-static int launch_steps(fdlb_ctx *h, long nsteps, hipStream_t s) {
+static int launch_group_steps(fdlb_ctx *h, int G, long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++)
-    for (int stage = 1; stage <= 3; stage++)
-      for (int G = 0; G < 4; G++) {
-        if (h->nU[G] == 0) continue;
-        int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
-        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, s));
-        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
-      }
+    for (int stage = 1; stage <= 3; stage++) {
+      int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
+      HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, s));
+      HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
+    }
+  return FDLB_OK;
+}
+
+// The launch groups hold disjoint cases, so each group's steps form a chain of
+// their own: the first group runs on s, the others on their own streams, so
+// that the groups' kernels can overlap on the device.  s ends after all of
+// them (also under graph capture, where the events become graph edges).
+static int launch_steps(fdlb_ctx *h, long nsteps, hipStream_t s) {
+  int groups[4], ng = 0;
+  for (int G = 0; G < 4; G++)
+    if (h->nU[G] > 0) groups[ng++] = G;
+  if (ng == 0) return FDLB_OK;
+  bool split = ng > 1 && h->fork_ev;
+  for (int i = 1; i < ng && split; i++) split = h->gstream[groups[i]] && h->join_ev[groups[i]];
+  if (!split) {
+    for (int i = 0; i < ng; i++) { int r = launch_group_steps(h, groups[i], nsteps, s); if (r) return r; }
+    return FDLB_OK;
+  }
+  HIPCHK(hipEventRecord(h->fork_ev, s));
+  for (int i = 1; i < ng; i++) {
+    const int G = groups[i];
+    HIPCHK(hipStreamWaitEvent(h->gstream[G], h->fork_ev, 0));
+    int r = launch_group_steps(h, G, nsteps, h->gstream[G]);
+    if (r) return r;
+    HIPCHK(hipEventRecord(h->join_ev[G], h->gstream[G]));
+  }
+  int r = launch_group_steps(h, groups[0], nsteps, s);
+  if (r) return r;
+  for (int i = 1; i < ng; i++) HIPCHK(hipStreamWaitEvent(s, h->join_ev[groups[i]], 0));
   return FDLB_OK;
 }
 
@@ -396,6 +437,11 @@ extern "C" void fdlb_destroy(fdlb_handle h) {
   if (!h) return;
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
+  for (int G = 0; G < 4; G++) {
+    if (h->gstream[G]) (void)hipStreamDestroy(h->gstream[G]);
+    if (h->join_ev[G]) (void)hipEventDestroy(h->join_ev[G]);
+  }
+  if (h->fork_ev) (void)hipEventDestroy(h->fork_ev);
   delete h;
 }
 
