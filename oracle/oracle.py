@@ -84,6 +84,8 @@ def lib():
         L.orc_pr_dense.argtypes = [D]
         L.orc_inv_tau.restype = D
         L.orc_inv_tau.argtypes = [D, D, D, D, D]
+        L.orc_nbar.argtypes = [P, dp, dp]
+        L.orc_nbar.restype = None
         L.orc_target.argtypes = [P, dp, dp, dp, C.POINTER(D)]
         _lib = L
     return _lib
@@ -187,6 +189,14 @@ class Oracle:
         out = np.zeros(self.params["qy"] ** 2)
         lib().orc_kmat_table(self._h, out)
         return out.reshape(self.params["qy"], self.params["qy"])
+
+    def nbar(self, n):
+        """Revised-Enskog (Fischer-Methfessel) average density of a cell-average
+        density profile n[nx] on this oracle's grid."""
+        n = np.ascontiguousarray(n, dtype=np.float64)
+        out = np.zeros(self.params["nx"])
+        lib().orc_nbar(self._h, n, out)
+        return out
 
     def target(self, mom6, grad5):
         out = np.zeros(self.K)

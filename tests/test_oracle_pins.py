@@ -362,9 +362,10 @@ def test_uniform_maxwellian_is_invariant():
         assert np.max(np.abs(o.get_f() - f0)) < 1e-13
 
 
-@pytest.mark.parametrize("grid", [0, 1])
-def test_mass_conserved_at_diffuse_walls(grid):
-    cfg = I.config("C1", nx=32, grid=grid, stretch=1.5 if grid else 0.0, collision=I.SHAKHOV_DENSE)
+@pytest.mark.parametrize("grid,chi_mode", [(0, 0), (1, 0), (1, 1)])
+def test_mass_conserved_at_diffuse_walls(grid, chi_mode):
+    cfg = I.config("C1", nx=32, grid=grid, stretch=1.5 if grid else 0.0, collision=I.SHAKHOV_DENSE,
+                   chi_mode=chi_mode)
     o = O.Oracle(**cfg)
     o.set_state(I.smooth_fields(3, 32, amp=0.05), I.noise(4, o.K, 32, 1e-3))
     x, J = o.grid()
@@ -375,10 +376,12 @@ def test_mass_conserved_at_diffuse_walls(grid):
     assert abs(m1 - m0) < 1e-13 * m0
 
 
-def test_couette_mirror_symmetry():
+@pytest.mark.parametrize("chi_mode", [0, 1])
+def test_couette_mirror_symmetry(chi_mode):
     """Couette with U_L = -U_R, T_L = T_R from a mirror-symmetric state:
-    n, T even; u_y, P_xy... u_y odd in x (checks both upwind stencils)."""
-    cfg = I.config("C2", nx=32, qx_half=4, qy=4, qz=4)
+    n, T even; u_y, P_xy... u_y odd in x (checks both upwind stencils, and the
+    averaged density window in both directions)."""
+    cfg = I.config("C2", nx=32, qx_half=4, qy=4, qz=4, chi_mode=chi_mode)
     o = O.Oracle(**cfg)
     o.step(60)
     m = o.moments()
@@ -416,3 +419,70 @@ def test_free_molecular_fourier_heat_flux():
     exact = 2 * math.sqrt(2 / math.pi) * 1.0 * math.sqrt(TL * TR) * (math.sqrt(TL) - math.sqrt(TR))
     assert abs(exact - (-0.0816892594)) < 1e-9
     assert np.max(np.abs(m[4] - exact)) < 1e-9, (m[4], exact)
+
+
+# --------------------------------------------------------------------------
+# P-RET  revised Enskog (Fischer-Methfessel) average density, eq:chi_ret
+# --------------------------------------------------------------------------
+def _faces(cfg, Lc):
+    """Cell faces of the grid (uniform, or tanh-stretched toward the walls)."""
+    eta = np.linspace(-1.0, 1.0, cfg["nx"] + 1)
+    if cfg["grid"] == 1 and cfg["stretch"] > 0:
+        d = cfg["stretch"]
+        return 0.5 * Lc * np.tanh(d * eta) / np.tanh(d)
+    return 0.5 * Lc * eta
+
+
+@pytest.mark.parametrize("grid", [0, 1])
+def test_nbar_of_uniform_density_is_the_clipped_sphere_fraction(grid):
+    """n = 1: the average is the part of the sphere of radius sigma around x
+    that lies inside the accessible width [-L_c/2, L_c/2], integrated over the
+    whole window at once: 3/(4 s^3) [G(min(s, d_r)) - G(-min(s, d_l))],
+    G(t) = s^2 t - t^3/3.  Next to a wall this is 1/2 + 3d/(4s) - d^3/(4s^3);
+    cells whose window lies inside get exactly 1."""
+    cfg = dict(I.config("C2", nx=96, grid=grid, stretch=1.5 if grid else 0.0), chi_mode=1)
+    o = O.Oracle(**{k: v for k, v in cfg.items() if k != "precision"})
+    sg, Lc = o.sigma, o.Lc
+    x, _ = o.grid()
+    nb = o.nbar(np.ones(cfg["nx"]))
+    G = lambda t: sg * sg * t - t ** 3 / 3
+    dl, dr = x + Lc / 2, Lc / 2 - x
+    want = 3 / (4 * sg ** 3) * (G(np.minimum(sg, dr)) - G(-np.minimum(sg, dl)))
+    assert np.max(np.abs(nb - want)) < 1e-13
+    near = dl < sg
+    half = 0.5 + 0.75 * dl / sg - 0.25 * dl ** 3 / sg ** 3
+    assert np.max(np.abs(nb[near & (dr >= sg)] - half[near & (dr >= sg)])) < 1e-13
+    inside = (dl >= sg) & (dr >= sg)
+    if np.any(inside):
+        assert np.max(np.abs(nb[inside] - 1.0)) < 1e-13
+
+
+def test_nbar_brute_force_on_a_stretched_grid():
+    """Random cell densities: the average by adaptive quadrature of the
+    piecewise-constant profile times the weight, over the clipped window."""
+    cfg = dict(I.config("C2", nx=40), chi_mode=1)
+    o = O.Oracle(**{k: v for k, v in cfg.items() if k != "precision"})
+    sg, Lc = o.sigma, o.Lc
+    xf = _faces(cfg, Lc)
+    x, _ = o.grid()
+    n = 1.0 + 0.3 * np.random.default_rng(5).random(cfg["nx"])
+    nb = o.nbar(n)
+    def dens(t):
+        j = np.searchsorted(xf, t, side="right") - 1
+        return n[min(max(j, 0), cfg["nx"] - 1)]
+    for i in (0, 3, 17, 20, 39):
+        a, b = max(x[i] - sg, -Lc / 2), min(x[i] + sg, Lc / 2)
+        pts = [t for t in xf if a < t < b]
+        val = integrate.quad(lambda t: dens(t) * (sg * sg - (t - x[i]) ** 2), a, b, points=pts,
+                             limit=400, epsabs=1e-14, epsrel=1e-13)[0]
+        assert abs(nb[i] - 3 / (4 * sg ** 3) * val) < 1e-11, i
+
+
+def test_ret_chi_reduces_to_local_chi_in_the_dilute_limit():
+    """eta0 -> 0: chi -> 1 either way, so the two closures give the same
+    step to the order of eta0."""
+    base = dict(I.config("C1", nx=24), eta0=1e-7)
+    a = O.Oracle(**dict(base, chi_mode=0))
+    b = O.Oracle(**dict(base, chi_mode=1))
+    a.step(20); b.step(20)
+    assert np.max(np.abs(a.moments() - b.moments())) < 1e-9
