@@ -66,7 +66,10 @@ typedef struct {
   int qx_half, qy, qz;       /* half-range order per half (1..32); full-range orders (2..8) */
   int collision;             /* fdlb_collision */
   double pr_fixed;           /* Prandtl number for FDLB_SHAKHOV_FIXED_PR */
-  int chi_mode;              /* 0: local Carnahan-Starling chi(eta0 n(x)) */
+  int chi_mode;              /* 0: local Carnahan-Starling chi(eta0 n(x)) (eq:chi); 1: revised
+                                Enskog theory, chi(eta0 nbar(x)) with the Fischer-Methfessel
+                                average density (eq:chi_ret) over |x'-x| < sigma, n = 0 outside
+                                the accessible width; nx <= 4000 */
   int j1_shear;              /* 1: keep the xi_x xi_y du_y/dx term of J1 (3D operator) */
   double cfl, dt;            /* dt > 0 overrides dt = cfl * min cell / max |p_x| */
   int precision;             /* fdlb_precision */

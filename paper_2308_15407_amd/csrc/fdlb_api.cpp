@@ -45,6 +45,10 @@ struct fdlb_ctx {
   // always runs the same kernel instance whatever else is in the batch
   int *d_mapT[4] = {nullptr, nullptr, nullptr, nullptr}, *d_mapU[4] = {nullptr, nullptr, nullptr, nullptr};
   int nT[4] = {0, 0, 0, 0}, nU[4] = {0, 0, 0, 0};
+  // revised Enskog cases: averaged-density blocks per group and their LDS
+  int *d_mapN[4] = {nullptr, nullptr, nullptr, nullptr};
+  int nN[4] = {0, 0, 0, 0};
+  size_t lds_n[4] = {0, 0, 0, 0};
   size_t lds[4] = {0, 0, 0, 0};   // dynamic LDS bytes of each group's update launch
   int waves = 4;
   int kx_user = 0;
@@ -68,7 +72,7 @@ static size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 enum {
   A_LAT, A_INVDX, A_F64_0, A_F64_1, A_F64_2, A_TX64, A_TYZ64, A_IT64, A_GW64_0, A_GW64_1,
   A_F32_0, A_F32_1, A_F32_2, A_TX32, A_TYZ32, A_IT32, A_GW32_0, A_GW32_1,
-  A_PART, A_MOM, A_FIELDS, A_COUNT
+  A_PART, A_MOM, A_FIELDS, A_NBAR, A_COUNT
 };
 
 static void case_sizes(const CaseHost &c, size_t *sz) {
@@ -92,13 +96,15 @@ static void case_sizes(const CaseHost &c, size_t *sz) {
   sz[A_PART] = nkx * NRAW * nx * 8;  // enough for one chunk per kx
   sz[A_MOM] = FDLB_NMOM * nx * 8;
   sz[A_FIELDS] = 6 * nx * 8;
+  sz[A_NBAR] = c.p.chi_mode == 1 ? nx * 8 : 0;
 }
 
 static size_t map_entries(const std::vector<CaseHost> &cs) {
   size_t n = 0;
   for (auto &c : cs) {
     const int nkx = 2 * c.qh;
-    n += (size_t)((c.nx + CTILE - 1) / CTILE + 2) + (size_t)((c.nx + UTILE - 1) / UTILE) * nkx;
+    n += (size_t)((c.nx + CTILE - 1) / CTILE + 2) + (size_t)((c.nx + UTILE - 1) / UTILE) * nkx +
+         (size_t)((c.nx + NBAR_TILE - 1) / NBAR_TILE);
   }
   return 2 * n + 2 * 64;  // room for both precision groups and XCD padding
 }
@@ -183,8 +189,8 @@ static std::vector<int> xcd_interleave(const std::vector<int> &logical) {
 
 static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
-  std::vector<int> mt[4], mu[4];
-  for (int G = 0; G < 4; G++) h->lds[G] = update_lds_bytes(G >> 1, 1, 1, h->waves, false);
+  std::vector<int> mt[4], mu[4], mn[4];
+  for (int G = 0; G < 4; G++) { h->lds[G] = update_lds_bytes(G >> 1, 1, 1, h->waves, false); h->lds_n[G] = 0; }
   for (size_t ci = 0; ci < h->cases.size(); ci++) {
     CaseHost &c = h->cases[ci];
     CaseDev &d = h->hdev[ci];
@@ -210,10 +216,19 @@ static int build_maps(fdlb_ctx *h) {
     mt[P].insert(mt[P].end(), {(int)ci, -2, 0, 0});
     for (int t = 0; t < nut; t++)
       for (int ch = 0; ch < c.nchunk; ch++) mu[P].insert(mu[P].end(), {(int)ci, t, ch, 0});
+    if (d.chi_mode == 1) {
+      // averaged-density blocks: the LDS holds the densities of a tile's window
+      for (int t = 0; t * NBAR_TILE < c.nx; t++) {
+        const int i0 = t * NBAR_TILE, i1 = std::min(i0 + NBAR_TILE, c.nx) - 1;
+        const size_t wlen = (size_t)(c.lat[c.lo.whi + i1] - c.lat[c.lo.wlo + i0]) + 1;
+        h->lds_n[P] = std::max(h->lds_n[P], (2 * wlen + 1) * sizeof(double));
+        mn[P].insert(mn[P].end(), {(int)ci, t, 0, 0});
+      }
+    }
   }
   for (int P = 0; P < 4; P++) mu[P] = xcd_interleave(mu[P]);
   size_t need = 0;
-  for (int P = 0; P < 4; P++) need += (mt[P].size() + mu[P].size()) / 4;
+  for (int P = 0; P < 4; P++) need += (mt[P].size() + mu[P].size() + mn[P].size()) / 4;
   if (need > h->map_cap) return fail(FDLB_ENOMEM, "launch map exceeds its reserved space");
   size_t off = 0;
   for (int P = 0; P < 4; P++) {
@@ -227,6 +242,11 @@ static int build_maps(fdlb_ctx *h) {
     if (!mu[P].empty())
       HIPCHK(hipMemcpyAsync(h->d_mapU[P], mu[P].data(), mu[P].size() * 4, hipMemcpyHostToDevice, h->stream));
     off += mu[P].size() / 4;
+    h->d_mapN[P] = h->d_map + 4 * off;
+    h->nN[P] = (int)(mn[P].size() / 4);
+    if (!mn[P].empty())
+      HIPCHK(hipMemcpyAsync(h->d_mapN[P], mn[P].data(), mn[P].size() * 4, hipMemcpyHostToDevice, h->stream));
+    off += mn[P].size() / 4;
   }
   int ng = 0;
   for (int G = 0; G < 4; G++) ng += h->nU[G] > 0;
@@ -250,6 +270,7 @@ static int launch_group_steps(fdlb_ctx *h, int G, long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++)
     for (int stage = 1; stage <= 3; stage++) {
       int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
+      if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], s));
       HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, s));
       HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
     }
@@ -405,6 +426,9 @@ extern "C" int fdlb_init(const fdlb_params *ps, int ncases, void *dev_ws, size_t
     d.part = (double *)arr[A_PART];
     d.mom = (double *)arr[A_MOM];
     d.nw[0] = d.nw[1] = 1.0;
+    d.chi_mode = (c.p.chi_mode == 1 && c.sigma > 0) ? 1 : 0;   // sigma = 0: the average is the local density
+    d.sigma = c.sigma;
+    d.nbar = (double *)arr[A_NBAR];
     d.resid = h->d_resid + i;
     d.fields = (double *)arr[A_FIELDS];
     d.noise = (double *)arr[A_F64_1];   // f^(1) is free while a state is being set
@@ -847,6 +871,7 @@ extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
         if (h->nU[G] == 0) continue;
         const int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
         hipEvent_t *e = ev[stage - 1][G];
+        if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], h->stream));
         HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->stream, e[0], e[1]));
         HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream,
                              e[2], e[3]));

@@ -40,6 +40,8 @@ struct LatOff {
   int ck;           // 1/h_Q'(p_k) [qh]
   int Hy, Hz;       // w_k He_l(p_k)/l!  [qy*qy], [qz*qz]
   int fdw;          // one-sided 7-point first-derivative weights, rows for cells 0,1,2 [3*7]
+  int xf, xcn;      // cell faces [nx+1] and centres [nx]
+  int wlo, whi;     // per cell, the first and last cell its averaging window overlaps [nx] each
   int phi;          // moment weights of every velocity [K][8] (64-byte rows): px, py, px^2, px py,
                     // py^2, pz^2, px |p|^2, py |p|^2 (the weight of the density sum is 1)
   int bg;           // background populations [K] (the case's uniform initial state); FP32 storage
@@ -61,6 +63,9 @@ struct CaseDev {
   double eta0, kn, chi0, pr_fixed, ay, dt;
   double tau_pre;       // (5 sqrt(2 pi)/16) Kn chi0 ; 0 when Kn = infinity
   double wallD[2];      // sum over emitted nodes of p_x g^w (left, right)
+  int chi_mode;         // 0: chi(eta0 n); 1: chi(eta0 nbar), the revised Enskog average
+  double sigma;         // molecular diameter in units of the channel width (1/R)
+  double *nbar;         // [nx] average density of the current stage input (chi_mode 1)
   double nw[2];         // wall densities of the current stage input, written by the table
                         // pass's wall blocks; kept in the record so the update reads them
                         // with the other fields

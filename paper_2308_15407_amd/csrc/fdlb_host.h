@@ -45,6 +45,11 @@ enum {
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
                         hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+// averaged density of the revised Enskog contact value (chi_mode 1 cases):
+// one block per NBAR_TILE cells; lds = bytes of the largest window of a tile
+constexpr int NBAR_TILE = 16;
+constexpr size_t NBAR_LDS_MAX = 65536;
+hipError_t launch_nbar(int prec, const CaseDev *cases, const int *map, int nblocks, size_t lds, hipStream_t s);
 // dynamic LDS of an update launch: partial sums of the waves, or the staged
 // projection tables of a tile when tlds (at most UPDATE_LDS_MAX bytes)
 constexpr size_t UPDATE_LDS_MAX = 65536;

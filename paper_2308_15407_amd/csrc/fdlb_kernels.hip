@@ -232,6 +232,69 @@ __device__ __forceinline__ void full_axis_values(double u, double T, int q, cons
     }
 }
 
+// Revised Enskog average density (chi_mode 1 cases; eq:chi_ret and the
+// average that follows it, reduced to the slab):
+//   nbar_i = 3/(4 sigma^3) sum_j n_j int_{cell j, |x'-x_i| < sigma} (sigma^2 - (x'-x_i)^2) dx',
+// with n_j the density of the stage input from the chunk partials (added in
+// chunk order, as the table pass does).  One 8-wave block per NBAR_TILE cells:
+// the densities and faces of the tile's window go to LDS, then each wave takes
+// one cell at a time with its lanes striding over the cell's window.
+template <typename T>
+__global__ void __launch_bounds__(512) k_nbar(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
+  // LDS: densities [nwin] and faces [nwin + 1] of the tile's window, and the
+  // centre and window range of each cell of the tile
+  extern __shared__ double s_n[];
+  __shared__ double s_x[NBAR_TILE];
+  __shared__ int s_lo[NBAR_TILE], s_hi[NBAR_TILE];
+  const int4 bm = map[blockIdx.x];
+  const CaseDev &c = cases[max(bm.x, 0)];
+  if (bm.x < 0) return;
+  const int nx = c.nx, c0 = bm.y * NBAR_TILE, c1 = min(c0 + NBAR_TILE, nx);
+  const GAS double *lat = gp<double>(c.lat);
+  const int jmin = (int)lat[c.lo.wlo + c0], jmax = (int)lat[c.lo.whi + c1 - 1];
+  const int nwin = jmax - jmin + 1, nch = c.nchunk;
+  double *s_f = s_n + nwin;
+  const double bg0 = sizeof(T) == 4 ? lat[c.lo.bgm] : 0.0;
+  const int tid = threadIdx.x;
+  if (tid < c1 - c0) {
+    s_x[tid] = lat[c.lo.xcn + c0 + tid];
+    s_lo[tid] = (int)lat[c.lo.wlo + c0 + tid];
+    s_hi[tid] = (int)lat[c.lo.whi + c0 + tid];
+  }
+  for (int q = tid; q <= nwin; q += blockDim.x) s_f[q] = lat[c.lo.xf + jmin + q];
+  // up to PB chunk loads in flight per thread (the chunk count is uniform)
+  constexpr int PB = 16;
+  for (int q = tid; q < nwin; q += blockDim.x) {
+    const GAS double *pp = gp<double>(c.part) + jmin + q;   // raw density row of chunk 0
+    double a = 0.0;
+    for (int ch0 = 0; ch0 < nch; ch0 += PB) {
+      double v[PB];
+#pragma unroll
+      for (int k = 0; k < PB; k++)
+        if (ch0 + k < nch) v[k] = pp[(size_t)(ch0 + k) * NRAW * nx];
+#pragma unroll
+      for (int k = 0; k < PB; k++)
+        if (ch0 + k < nch) a += v[k];
+    }
+    s_n[q] = a + bg0;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  const double sg = c.sigma, s2 = sg * sg;
+  for (int i = c0 + wv; i < c1; i += nwv) {
+    const double x = s_x[i - c0];
+    const int lo = s_lo[i - c0] - jmin, hi = s_hi[i - c0] - jmin;
+    double acc = 0.0;
+    for (int q = lo + lane; q <= hi; q += 64) {
+      const double a = fmax(s_f[q], x - sg) - x, b = fmin(s_f[q + 1], x + sg) - x;
+      acc += s_n[q] * ((s2 * b - b * b * b / 3.0) - (s2 * a - a * a * a / 3.0));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) c.nbar[i] = 3.0 / (4.0 * sg * s2) * acc;
+  }
+}
+
 template <typename T, int NT>
 __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
                                                int mode, int gin) {
@@ -246,6 +309,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   constexpr int W = CTILE + 2 * CHALO;
   __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy
   __shared__ double s_l[3][W];      // ln n, ln chi, ln T
+  __shared__ double s_chi[W];       // contact value chi
   __shared__ double s_c[CTILE][20]; // n, ux, uy, T, invtau, C[13]
   // the raw sums of the tile and its halo first, then the base weights G
   // (rows padded by one double so that lanes reading different cells or
@@ -297,6 +361,10 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   double bgs[NRAW];
 #pragma unroll
   for (int m = 0; m < NRAW; m++) bgs[m] = sizeof(T) == 4 ? glat[lo.bgm + m] : 0.0;
+  // revised Enskog cases: chi takes the average density of the stage input
+  const bool ret = c.chi_mode == 1 && (mode & TM_PARTIALS);
+  double nbv = 0.0;
+  if (ret && tid < W) nbv = gp<double>(c.nbar)[min(max(c0 - CHALO + tid, 0), nx - 1)];
   // one thread per (raw moment, cell of the tile and halo) adds the chunk
   // partials in chunk order; up to PB chunk loads are in flight at a time
   // (the chunk count is uniform, so the guards are scalar branches)
@@ -363,7 +431,9 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
         qy_ = 0.5 * (S[8] - 2.0 * (ux * S[4] + uy * S[5]) - uy * S2 + 2.0 * n * uy * u2);
       }
       s_m[0][tid] = n; s_m[1][tid] = ux; s_m[2][tid] = uy; s_m[3][tid] = T_; s_m[4][tid] = qx; s_m[5][tid] = qy_;
-      s_l[0][tid] = log(n); s_l[1][tid] = log(chi_cs(c.eta0 * n)); s_l[2][tid] = log(T_);
+      const double chi = chi_cs(c.eta0 * (ret ? nbv : n));
+      s_chi[tid] = chi;
+      s_l[0][tid] = log(n); s_l[1][tid] = log(chi); s_l[2][tid] = log(T_);
       const bool owned = tid >= CHALO && tid < CHALO + own;
       if (owned && (mode & TM_RESID)) {
         const double *mo = c.mom;
@@ -435,7 +505,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
         }
         g[q] = d * dxi_own;
       }
-      const double eta = c.eta0 * n, chi = chi_cs(eta);
+      const double eta = c.eta0 * n, chi = s_chi[li];
       const double brc = 4.0 * eta * chi;   // b rho chi
       double tau = 0.0;
       if (c.tau_pre > 0.0) {
@@ -1065,6 +1135,15 @@ template <typename K, typename... A>
 static void launch_k(K kern, dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1, A... args) {
   if (e0) hipExtLaunchKernelGGL(kern, g, b, (uint32_t)lds, s, e0, e1, 0u, args...);
   else hipLaunchKernelGGL(kern, g, b, lds, s, args...);
+}
+
+hipError_t launch_nbar(int prec, const CaseDev *cases, const int *map, int nblocks, size_t lds, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (lds == 0 || lds > NBAR_LDS_MAX) return hipErrorInvalidValue;
+  const int4 *m = (const int4 *)map;
+  if (prec == 0) hipLaunchKernelGGL(k_nbar<double>, dim3(nblocks), dim3(512), lds, s, cases, m);
+  else hipLaunchKernelGGL(k_nbar<float>, dim3(nblocks), dim3(512), lds, s, cases, m);
+  return hipGetLastError();
 }
 
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,

@@ -164,7 +164,8 @@ int validate(const fdlb_params &p, std::string &why, double *sigma, double *R) {
   if (p.grid != 0 && p.grid != 1) { why = "unknown grid"; return -1; }
   if (p.grid == 1 && !(p.stretch > 0)) { why = "tanh grid needs stretch > 0"; return -1; }
   if (p.precision != 0 && p.precision != 1) { why = "unknown precision"; return -1; }
-  if (p.chi_mode != 0) { why = "only the local Carnahan-Starling chi is implemented"; return -1; }
+  if (p.chi_mode != 0 && p.chi_mode != 1) { why = "chi_mode must be 0 (local) or 1 (revised Enskog average)"; return -1; }
+  if (p.chi_mode == 1 && p.nx > 4000) { why = "chi_mode 1 supports nx <= 4000 (averaging windows are staged in LDS)"; return -1; }
   if (!(p.t_left > 0 && p.t_right > 0 && p.t_init > 0 && p.n_init > 0)) { why = "temperatures and density must be positive"; return -1; }
   if (!(p.dt > 0) && !(p.cfl > 0)) { why = "need cfl > 0 or dt > 0"; return -1; }
   double s = 0, r = INFINITY;
@@ -206,6 +207,10 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   o.pz = off; off += c.qz;
   o.kmat = off; off += c.qy * c.qy;
   o.fdw = off; off += 3 * 7;
+  o.xf = off; off += c.nx + 1;     // cell faces
+  o.xcn = off; off += c.nx;        // cell centres
+  o.wlo = off; off += c.nx;        // first and last cell of each averaging window
+  o.whi = off; off += c.nx;
   off = (off + 7) & ~7;   // 64-byte aligned rows (one scalar load per velocity)
   o.phi = off; off += c.K * 8;
   o.bg = off; off += c.K;
@@ -318,6 +323,19 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     hmin = fmin(hmin, c.jac[i] * c.deta);
   }
   c.dt = p.dt > 0 ? p.dt : p.cfl * hmin / fabs(L[o.px + Q - 1]);
+  // averaging geometry of the revised Enskog contact value (faces, centres and
+  // the cells each window |x' - x_i| < sigma overlaps; ranges stored as doubles)
+  for (int j = 0; j <= c.nx; j++) {
+    const double eta = -1 + j * c.deta;
+    L[o.xf + j] = p.grid == 1 ? 0.5 * c.Lc * tanh(p.stretch * eta) / tanh(p.stretch) : 0.5 * c.Lc * eta;
+  }
+  for (int i = 0; i < c.nx; i++) {
+    L[o.xcn + i] = c.x[i];
+    int lo = i, hi = i;
+    while (lo > 0 && L[o.xf + lo] > c.x[i] - sigma) lo--;
+    while (hi < c.nx - 1 && L[o.xf + hi + 1] < c.x[i] + sigma) hi++;
+    L[o.wlo + i] = lo; L[o.whi + i] = hi;
+  }
   // wall Maxwellians at (u_x = 0, u_y = U_w, T_w) with n = 1, and the emitted flux
   // denominators sum_{emitted} p_x g^w
   for (int wall = 0; wall < 2; wall++) {

@@ -159,3 +159,24 @@ def test_largest_velocity_sets(flow, prec):
             assert err[k] < 1e-5, (k, err[k])
         for k in ("ux", "qx"):
             assert err[k] < 1e-4, (k, err[k])
+
+
+@pytest.mark.parametrize("base,kw,prec", [("C2", dict(nx=80, qx_half=6), 0), ("C1", dict(nx=64), 0),
+                                          ("C3", dict(nx=48, qx_half=5, qy=6, qz=4), 0),
+                                          ("C2", dict(nx=80, qx_half=6), 1)])
+def test_revised_enskog_chi(base, kw, prec):
+    """chi_mode 1: chi from the revised Enskog (Fischer-Methfessel) average
+    density, computed on the GPU by its own pass from the chunk partials."""
+    cfg = dict(I.config(base, **kw), chi_mode=1, precision=prec)
+    s, o = _pair(cfg, 12)
+    s.step(15)
+    o.step(15)
+    if prec == 0:
+        _compare(s, o, TOL64, "%s chi_mode 1" % base)
+    else:
+        err = rel_moment_errors(s.moments(0), o.moments())
+        print("%s chi_mode 1 FP32" % base, {k: "%.1e" % v for k, v in err.items()}, flush=True)
+        for k in ("n", "uy", "T", "Pxy"):
+            assert err[k] < 1e-5, (k, err[k])
+        for k in ("ux", "qx"):
+            assert err[k] < 1e-4, (k, err[k])

@@ -172,3 +172,33 @@ def test_autotuner_picks_a_candidate_and_results_do_not_depend_on_tiling(tmp_pat
         a, b = s2.moments(c), ref.moments(c)
         tol = 1e-12 if c == 0 else 1e-6
         assert np.max(np.abs(a[0] - b[0]) / b[0]) < tol and np.max(np.abs(a[3] - b[3]) / b[3]) < tol
+
+
+def test_revised_enskog_gas_at_rest_layers_at_the_walls():
+    """Dense gas at rest between walls at T = 1 (eta0 = 0.2, R = 4): with the
+    local contact value the uniform state is stationary; with the revised
+    Enskog average the steady density rises toward the walls and is
+    non-monotonic across the half channel (the layering the paper describes
+    for its gas-at-rest case; its particle-method curves are not available,
+    so only the shape and mass conservation are checked)."""
+    from paper_2308_15407_amd.solver import Solver
+    eta0, R = 0.2, 4.0
+    chi0 = 0.5 * (2 - eta0) / (1 - eta0) ** 3
+    kn = 1 / (6 * np.sqrt(2) * eta0 * chi0 * R)
+    out = {}
+    for cm in (0, 1):
+        cfg = dict(I.BASE, flow=0, nx=128, grid=0, qx_half=8, qy=4, qz=4, kn=kn, eta0=eta0, t_left=1.0,
+                   t_right=1.0, t_init=1.0, uy_init=0.0, collision=0, chi_mode=cm)
+        s = Solver(cfg, graph_steps=50)
+        st, res, code = s.run_to_steady(tol=1e-8, max_steps=60000, check_every=500)
+        assert code == 0 and res[0] < 1e-8, (cm, st, res, code)
+        out[cm] = (s.moments(0)[0], s.mass())
+    n0, m0 = out[0]
+    assert np.max(np.abs(n0 - 1.0)) < 1e-10
+    n1, m1 = out[1]
+    assert abs(m1 - m0) < 1e-9 * m0                            # mass is kept
+    half = n1[:64]
+    assert np.max(np.abs(n1 - n1[::-1])) < 1e-9            # symmetric channel
+    assert half[0] > half[-1] + 0.05                          # denser at the wall
+    imin = int(np.argmin(half))
+    assert 0 < imin < 63 and half[-1] > half[imin] + 1e-4     # a dip before the centre
