@@ -69,7 +69,10 @@ typedef struct {
   int chi_mode;              /* 0: local Carnahan-Starling chi(eta0 n(x)) (eq:chi); 1: revised
                                 Enskog theory, chi(eta0 nbar(x)) with the Fischer-Methfessel
                                 average density (eq:chi_ret) over |x'-x| < sigma, n = 0 outside
-                                the accessible width; nx <= 4000 */
+                                the accessible width; nx <= 4000.  With 1 the layered density
+                                of a dense case can leave the residual of fdlb_run_to_steady
+                                stalled at 1e-6 .. 1e-4 (WENO weights switching at its
+                                extrema) while the moments have settled */
   int j1_shear;              /* 1: keep the xi_x xi_y du_y/dx term of J1 (3D operator) */
   double cfl, dt;            /* dt > 0 overrides dt = cfl * min cell / max |p_x| */
   int precision;             /* fdlb_precision */

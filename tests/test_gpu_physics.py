@@ -202,3 +202,29 @@ def test_revised_enskog_gas_at_rest_layers_at_the_walls():
     assert half[0] > half[-1] + 0.05                          # denser at the wall
     imin = int(np.argmin(half))
     assert 0 < imin < 63 and half[-1] > half[imin] + 1e-4     # a dip before the centre
+
+
+def test_batch_with_both_contact_values_matches_single_bitwise():
+    """A batch mixing local and revised-Enskog cases (FP64 and FP32, one with
+    eta0 = 0, where the average falls back to the local density) advances
+    every case exactly as it advances alone."""
+    cfgs = [dict(I.config("C2", nx=70, qx_half=5), chi_mode=1), dict(I.config("C1", nx=40), chi_mode=0),
+            dict(I.config("C2", nx=50, qx_half=4, precision=1), chi_mode=1),
+            dict(I.BASE, nx=30, qx_half=3, qy=3, qz=3, kn=0.3, eta0=0.0, t_right=1.2, chi_mode=1)]
+    b = _solver(cfgs)
+    singles = [_solver(c) for c in cfgs]
+    for i, c in enumerate(cfgs):
+        K = 2 * c["qx_half"] * c["qy"] * c["qz"]
+        fields, noise = seeded_state(50 + i, c["nx"], K)
+        b.set_state(i, fields, noise)
+        singles[i].set_state(0, fields, noise)
+    b.step(23)
+    for i, s in enumerate(singles):
+        s.step(23)
+        assert np.array_equal(b.get_f(i), s.get_f(0)), i
+    # eta0 = 0: identical to the local closure
+    loc = _solver(dict(cfgs[3], chi_mode=0))
+    fields, noise = seeded_state(53, 30, 54)
+    loc.set_state(0, fields, noise)
+    loc.step(23)
+    assert np.array_equal(loc.get_f(0), singles[3].get_f(0))

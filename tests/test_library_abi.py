@@ -37,6 +37,11 @@ def test_validation_errors():
         F.fdlb_case_info(dict(I.BASE, kn=0.0, eta0=0.1))      # Kn = inf needs eta0 = 0
     with pytest.raises(F.FdlbError):
         F.fdlb_case_info(dict(I.BASE, qy=9))
+    with pytest.raises(F.FdlbError):
+        F.fdlb_case_info(dict(I.BASE, chi_mode=2))                # unknown contact value
+    with pytest.raises(F.FdlbError):
+        F.fdlb_case_info(dict(I.BASE, chi_mode=1, nx=4096))       # averaging windows in LDS
+    assert F.fdlb_case_info(dict(I.BASE, chi_mode=1, nx=4000))["K"] == 72
     assert F.fdlb_case_info(I.config("C1"))["K"] == 72
 
 
