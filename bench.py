@@ -35,6 +35,7 @@ def parse():
     ap.add_argument("--large-steps", type=int, default=60)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=100)
+    ap.add_argument("--r1-steps", type=int, default=20)
     ap.add_argument("--tts-batch", type=int, default=64, help="held-out cases in the learned time-to-steady leg")
     ap.add_argument("--tts-seq", type=int, default=8, help="cases solved one at a time by the plain FP64 leg")
     return ap.parse_args()
@@ -128,6 +129,24 @@ def sweep_leg(steps, retune):
             "nodes": nodes, "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}}
 
 
+def sweep_r1_leg(steps, retune, ncases=1024):
+    """The sweep generator at 1024 cases (FP32 bulk, about 0.3 GB per population
+    array, beyond the 256 MB Infinity Cache): whole-step throughput, and the
+    algorithmic bytes of a step (8 passes x 4 B per node) over its time as an
+    effective bandwidth (the table passes included, so a lower bound on the
+    update kernels' rate)."""
+    from paper_2308_15407_amd import sweep
+    cases = sweep.sweep_cases(ncases)
+    s, ms, nodes, tile, prof = measure(cases, steps, 5, retune, graph_steps=10)
+    eff = 8 * 4 * nodes / (ms * 1e-3) / 1e9
+    return {"workload": "sweep: %d seeded cases (PCG64 %d, R >= 2), Nx 64-512, Q_x^h 4-16 x 4 x 4, FP32 bulk"
+                        % (ncases, sweep.SWEEP_SEED),
+            "value": round(nodes / (ms * 1e-3), 1), "unit": "node-velocity updates/s", "ms_per_step": round(ms, 5),
+            "nodes": nodes, "f_array_bytes": 4 * sum(c["nx"] * 2 * c["qx_half"] * c["qy"] * c["qz"] for c in cases),
+            "effective_GBps_whole_step": round(eff, 1), "frac_of_hbm_peak": round(eff / HBM_PEAK_GBS, 4),
+            "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}}
+
+
 def time_to_steady_leg(n_batch, n_seq, tol=1e-8, max_steps=400000):
     """Wall-clock time to r < tol per case: plain FP64 cold start (one case at a
     time, a sample of n_seq cases) against batched FP32 bulk + learned warm
@@ -208,6 +227,7 @@ def main():
                 "roofline": roofline(profL, nodesL, prec, "k_update<%s,2>" % ("double" if prec == 0 else "float"), "R2"),
                 "kernel_ms": {"table": round(profL[0], 5), "update": [round(x, 5) for x in profL[1 + 3 * prec:4 + 3 * prec]]}}
         out["sweep"] = sweep_leg(args.sweep_steps, args.retune)
+        out["sweep_r1"] = sweep_r1_leg(args.r1_steps, args.retune)
         out["time_to_steady"] = time_to_steady_leg(args.tts_batch, args.tts_seq)
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg)
     print(json.dumps(out))
