@@ -332,11 +332,12 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   const int qh = c.qh, qy = c.qy, qz = c.qz;
 
   // Every global read of the kernel is issued first so that the latencies
-  // overlap: the lattice constants (flat index over lambda, the base nodes,
-  // p_k / c_k, H_y, H_z), the chunk partials of the tile and its halo, and the
-  // metric and wall FD weights of the owned cells.  Three phases follow:
-  // moments; closure (first wave) beside the base weights (other waves); the
-  // X and YZ tables.
+  // overlap: the lattice constants (one contiguous block: p_x, the base
+  // nodes, lambda, c_k, H_y, H_z), the metric and wall FD weights of the
+  // owned cells, the average density (revised Enskog cases) and the chunk
+  // partials of the tile and its halo.  Three phases follow: moments;
+  // closure (first wave) beside the base weights (other waves); the X and YZ
+  // tables.
   const GAS double *glat = gp<double>(lat);
   constexpr int CB = 2048 / NT;
   static_assert(CB * NT >= 3 * MAXQH + 3 * NB + MAXQH * NB + 2 * MAXQY * MAXQY, "constant staging");
