@@ -37,7 +37,7 @@ DEFAULT_OUT = os.path.join(HERE, "mfr_results.json")
 R_VALUES = (2.0, 5.0, 10.0, 20.0)
 KN_VALUES = tuple(float(v) for v in np.round(np.logspace(-2, math.log10(2.0), 12), 5))
 AY = 1e-3
-ETA_MAX = 0.25   # the explicit step diverges for the densest cases with either contact value
+ETA_MAX = 0.25   # the densest cases of this sweep diverge with either contact value, at any CFL
 
 
 def chi_cs(eta):
