@@ -63,7 +63,7 @@ typedef struct {
   double n_init, t_init, uy_init; /* uniform initial state (projected Maxwellian) */
   int nx, grid;              /* cells (>= 7) and fdlb_grid */
   double stretch;            /* tanh map parameter delta for FDLB_GRID_TANH */
-  int qx_half, qy, qz;       /* half-range order per half (1..32); full-range orders (2..8) */
+  int qx_half, qy, qz;       /* half-range order per half (1..200); full-range orders (2..8) */
   int collision;             /* fdlb_collision */
   double pr_fixed;           /* Prandtl number for FDLB_SHAKHOV_FIXED_PR */
   int chi_mode;              /* 0: local Carnahan-Starling chi(eta0 n(x)) (eq:chi); 1: revised

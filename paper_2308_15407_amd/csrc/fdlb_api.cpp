@@ -52,6 +52,7 @@ struct fdlb_ctx {
   size_t lds[4] = {0, 0, 0, 0};   // dynamic LDS bytes of each group's update launch
   int waves = 4;
   int kx_user = 0;
+  bool wide = false;          // some case has qx_half > MAXQH (wide table pass)
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -191,6 +192,8 @@ static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
   std::vector<int> mt[4], mu[4], mn[4];
   for (int G = 0; G < 4; G++) { h->lds[G] = update_lds_bytes(G >> 1, 1, 1, h->waves, false); h->lds_n[G] = 0; }
+  h->wide = false;
+  for (const CaseHost &c : h->cases) h->wide = h->wide || c.qh > MAXQH;
   for (size_t ci = 0; ci < h->cases.size(); ci++) {
     CaseHost &c = h->cases[ci];
     CaseDev &d = h->hdev[ci];
@@ -271,7 +274,7 @@ static int launch_group_steps(fdlb_ctx *h, int G, long nsteps, hipStream_t s) {
     for (int stage = 1; stage <= 3; stage++) {
       int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
       if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], s));
-      HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, s));
+      HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wide, s));
       HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
     }
   return FDLB_OK;
@@ -310,7 +313,7 @@ static int launch_moments(fdlb_ctx *h, bool resid) {
   if (resid) HIPCHK(launch_zero_resid(h->d_cases, (int)h->cases.size(), h->stream));
   for (int G = 0; G < 4; G++)
     HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G],
-                        TM_PARTIALS | TM_WRITE_MOM | (resid ? TM_RESID : 0), 0, h->stream));
+                        TM_PARTIALS | TM_WRITE_MOM | (resid ? TM_RESID : 0), 0, h->wide, h->stream));
   return FDLB_OK;
 }
 
@@ -362,9 +365,9 @@ static int set_state_dev(fdlb_ctx *h, int ci, const double *fields, const double
   int *tmp = h->d_map + 4 * (h->map_cap - (mt.size() + mu.size()) / 4);
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, c.qh > MAXQH, h->stream));
   HIPCHK(launch_fill(P, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, noise ? 1 : 0, h->stream));
-  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, c.qh > MAXQH, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   c.steps = 0;
   c.last_resid = INFINITY;
@@ -495,7 +498,8 @@ extern "C" int fdlb_moments(fdlb_handle h, int c, double *out) {
   for (int t = 0; t < (ch.nx + CTILE - 1) / CTILE; t++) mt.insert(mt.end(), {c, t, 0, 0});
   int *tmp = h->d_map + 4 * (h->map_cap - mt.size() / 4);
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, (int)(mt.size() / 4), TM_PARTIALS | TM_WRITE_MOM, 0, h->stream));
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, (int)(mt.size() / 4), TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH,
+                      h->stream));
   HIPCHK(hipMemcpyAsync(out, h->hdev[c].mom, sizeof(double) * FDLB_NMOM * ch.nx, hipMemcpyDeviceToHost, h->stream));
   if (!was) { h->hdev[c].active = 0; r = upload_cases(h); if (r) return r; }
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -628,7 +632,7 @@ static int refresh_partials(fdlb_ctx *h, int c) {
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(launch_partials(ch.prec, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, h->stream));
-  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, h->stream));
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return FDLB_OK;
 }
@@ -872,7 +876,8 @@ extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
         const int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
         hipEvent_t *e = ev[stage - 1][G];
         if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], h->stream));
-        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->stream, e[0], e[1]));
+        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wide, h->stream, e[0],
+                            e[1]));
         HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream,
                              e[2], e[3]));
       }

@@ -8,7 +8,15 @@
 namespace fdlb {
 
 constexpr int NB = 48;         // nodes of the half-range base rule used for projections
-constexpr int MAXQH = 32;      // largest half-range order per half
+constexpr int MAXQH = 32;      // largest half-range order per half of the standard tables
+// Orders above MAXQH (quadrature convergence studies) use the wide table
+// kernel: a base rule of NB_WIDE nodes, exact to degree 2 NB_WIDE - 1, so
+// that the projections onto h_l, l < Q, alias only through expansion terms of
+// degree >= 2 NB_WIDE - Q + 1 (>= 89 at Q = MAXQH_WIDE), which are below
+// rounding for the Maxwellians of wall temperature ratios up to 3.
+constexpr int MAXQH_WIDE = 200;
+constexpr int NB_WIDE = 144;
+__host__ __device__ inline int base_nodes(int qh) { return qh > MAXQH ? NB_WIDE : NB; }
 constexpr int MAXQY = 8;       // largest full-range order on y and z
 constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
 #ifndef FDLB_CTILE
@@ -34,9 +42,9 @@ __host__ __device__ inline int fslots(int nx) { return 64 * ((nx + UTILE - 1) / 
 struct LatOff {
   int px, py, pz;   // node coordinates: [2qh], [qy], [qz]
   int kmat;         // momentum-derivative kernel [qy*qy] (App. A)
-  int bP, bA;       // base rule nodes P_m and A_m = ln W_m + P_m^2/2, [NB] each
-  int lam;          // Lagrange basis of the lattice nodes at the base nodes [qh*NB]
-  int hQ;           // h_Q at the base nodes [NB]
+  int bP, bA;       // base rule nodes P_m and A_m = ln W_m + P_m^2/2, [nb] each
+  int lam;          // Lagrange basis of the lattice nodes at the base nodes [qh*nb]
+  int hQ;           // h_Q at the base nodes [nb]
   int ck;           // 1/h_Q'(p_k) [qh]
   int Hy, Hz;       // w_k He_l(p_k)/l!  [qy*qy], [qz*qz]
   int fdw;          // one-sided 7-point first-derivative weights, rows for cells 0,1,2 [3*7]
@@ -115,17 +123,18 @@ __host__ __device__ inline void hermite_coeffs(double u, double T, int L, double
 inline void host_half_table(const double *lat, const LatOff &lo, int qh, double u, double T, int a,
                             double *X) {
   double rsT = 1.0 / sqrt(T);
+  const int nb = base_nodes(qh);
   for (int side = 0; side < 2; side++) {
     double us = side == 0 ? u : -u;
-    double G[NB], mb[3] = {0, 0, 0};
-    for (int m = 0; m < NB; m++) G[m] = base_weight(lat, lo, m, us, T, rsT);
-    for (int m = 0; m < NB; m++) {
+    double G[NB_WIDE], mb[3] = {0, 0, 0};
+    for (int m = 0; m < nb; m++) G[m] = base_weight(lat, lo, m, us, T, rsT);
+    for (int m = 0; m < nb; m++) {
       double d = lat[lo.bP + m] - us, h = lat[lo.hQ + m] * G[m];
       mb[0] += h; mb[1] += h * d; mb[2] += h * d * d;
     }
     for (int k = 0; k < qh; k++) {
       double x0 = 0;
-      for (int m = 0; m < NB; m++) x0 += G[m] * lat[lo.lam + k * NB + m];
+      for (int m = 0; m < nb; m++) x0 += G[m] * lat[lo.lam + k * nb + m];
       double dk = lat[lo.px + k] - us, ck = lat[lo.ck + k];
       double v;
       if (a == 0) v = x0;

@@ -43,8 +43,9 @@ enum {
 
 // kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
+// wide: the map may hold cases with qx_half > MAXQH (adds the wide pass)
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
-                        hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                        bool wide, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // averaged density of the revised Enskog contact value (chi_mode 1 cases):
 // one block per NBAR_TILE cells; lds = bytes of the largest window of a tile
 constexpr int NBAR_TILE = 16;

@@ -295,7 +295,12 @@ __global__ void __launch_bounds__(512) k_nbar(const CaseDev *__restrict__ cases,
   }
 }
 
-template <typename T, int NT>
+// WIDE = false serves half-range orders up to MAXQH with an NB-node base rule
+// and the Lagrange rows in LDS; WIDE = true serves the orders above (up to
+// MAXQH_WIDE) with an NB_WIDE-node base rule and the rows read from global
+// memory.  Both run on the same launch map; each skips the other's cases, and
+// the wall blocks of every case belong to the standard instantiation.
+template <typename T, int NT, bool WIDE>
 __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
                                                int mode, int gin) {
   // launch maps list only active cases; padding entries have bm.x < 0
@@ -303,9 +308,11 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   const CaseDev &c = cases[max(bm.x, 0)];
   if (bm.x < 0) return;
   if (bm.y < 0) {
-    if (mode & TM_WALLS) wall_block<T>(c, -bm.y - 1, gin);
+    if (!WIDE && (mode & TM_WALLS)) wall_block<T>(c, -bm.y - 1, gin);
     return;
   }
+  if ((c.qh > MAXQH) != WIDE) return;
+  constexpr int NBX = WIDE ? NB_WIDE : NB;   // base rule nodes
   constexpr int W = CTILE + 2 * CHALO;
   __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy
   __shared__ double s_l[3][W];      // ln n, ln chi, ln T
@@ -315,14 +322,16 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   // (rows padded by one double so that lanes reading different cells or
   // nodes fall in different banks)
   static_assert(NRAW * W <= 256, "one thread per raw moment and cell of the tile and halo");
-  constexpr int SCR = NRAW * W > CTILE * 2 * (NB + 1) ? NRAW * W : CTILE * 2 * (NB + 1);
+  constexpr int SCR = NRAW * W > CTILE * 2 * (NBX + 1) ? NRAW * W : CTILE * 2 * (NBX + 1);
   __shared__ double s_scr[SCR];
-  double (*s_G)[2][NB + 1] = reinterpret_cast<double (*)[2][NB + 1]>(s_scr);
+  double (*s_G)[2][NBX + 1] = reinterpret_cast<double (*)[2][NBX + 1]>(s_scr);
   __shared__ double s_red[NT];
   // lattice constants, staged by one linear copy of their contiguous block
   // [p_x (2 qh) | P_m | A_m | h_Q(P_m) | lambda (qh rows of NB) | c_k (qh) | H_y | H_z];
-  // the lambda rows are padded by one double in LDS (bank spread)
-  constexpr int NCST = 2 * MAXQH + 3 * NB + MAXQH * (NB + 1) + MAXQH + 2 * MAXQY * MAXQY;
+  // the lambda rows are padded by one double in LDS (bank spread); the wide
+  // instantiation leaves them in global memory and stages the rest
+  constexpr int NCST = WIDE ? 3 * MAXQH_WIDE + 3 * NBX + 2 * MAXQY * MAXQY
+                            : 2 * MAXQH + 3 * NB + MAXQH * (NB + 1) + MAXQH + 2 * MAXQY * MAXQY;
   __shared__ double s_cst[NCST];
   const int nx = c.nx, c0 = bm.y * CTILE;
   const int own = min(CTILE, nx - c0);
@@ -340,14 +349,15 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   // tables.
   const GAS double *glat = gp<double>(lat);
   constexpr int CB = 2048 / NT;
-  static_assert(CB * NT >= 3 * MAXQH + 3 * NB + MAXQH * NB + 2 * MAXQY * MAXQY, "constant staging");
-  const int cL0 = 2 * qh + 3 * NB, cL1 = cL0 + qh * NB, ncst = cL1 + qh + qy * qy + qz * qz;
+  static_assert(CB * NT >= (WIDE ? 3 * MAXQH_WIDE + 3 * NBX : 3 * MAXQH + 3 * NB + MAXQH * NB) +
+                                 2 * MAXQY * MAXQY, "constant staging");
+  const int cL0 = 2 * qh + 3 * NBX, cL1 = cL0 + (WIDE ? 0 : qh * NB), ncst = cL1 + qh + qy * qy + qz * qz;
   double cv[CB];
   if (mode & TM_TABLES) {
 #pragma unroll
     for (int u = 0; u < CB; u++) {
-      const int it = tid + u * NT;
-      cv[u] = glat[lo.px + min(it, ncst - 1)];
+      const int it = min(tid + u * NT, ncst - 1);
+      cv[u] = glat[WIDE && it >= cL0 ? lo.ck + (it - cL0) : lo.px + it];
     }
   }
   const int ci = c0 + tid;
@@ -392,7 +402,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
       const int it = tid + u * NT;
       if (it < ncst) {
         const int q = it - cL0;
-        const int dst = it < cL0 ? it : (it < cL1 ? cL0 + (q / NB) * (NB + 1) + q % NB : it + qh);
+        const int dst = WIDE ? it : (it < cL0 ? it : (it < cL1 ? cL0 + (q / NB) * (NB + 1) + q % NB : it + qh));
         s_cst[dst] = cv[u];
       }
     }
@@ -400,8 +410,8 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   if (!(mode & TM_FIELDS) && tid < NRAW * W) s_scr[pm * W + pw] = praw;
   __syncthreads();
 
-  const double *s_px = s_cst, *s_P = s_cst + 2 * qh, *s_A = s_P + NB, *s_hQ = s_A + NB;
-  const double *s_lam = s_hQ + NB, *s_ck = s_lam + qh * (NB + 1);
+  const double *s_px = s_cst, *s_P = s_cst + 2 * qh, *s_A = s_P + NBX, *s_hQ = s_A + NBX;
+  const double *s_lam = s_hQ + NBX, *s_ck = WIDE ? s_lam : s_lam + qh * (NB + 1);
   const double *s_Hy = s_ck + qh, *s_Hz = s_Hy + qy * qy;
 
   // ---- moments of the stage input for the tile and its halo ----
@@ -547,8 +557,8 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   } else if (tid >= 64) {
     // ---- half-range base weights per owned cell and half (waves 1..3) ----
     static_assert(CTILE <= 64, "the closure runs on the first wave");
-    for (int it = tid - 64; it < own * 2 * NB; it += NT - 64) {
-      const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
+    for (int it = tid - 64; it < own * 2 * NBX; it += NT - 64) {
+      const int cl = it / (2 * NBX), h = (it / NBX) & 1, m = it % NBX;
       const double ux = s_m[1][cl + CHALO], T_ = s_m[3][cl + CHALO];
       const double u = h == 0 ? ux : -ux;
       const double d = s_P[m] - u;
@@ -571,14 +581,25 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
       const int cl = it % own, rest = it / own, h = rest & 1, k0 = 2 * (rest >> 1);   // cell fastest
       const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
       const double *Gc = s_G[cl][h];
-      const double *l0 = s_lam + k0 * (NB + 1), *l1 = s_lam + min(k0 + 1, qh - 1) * (NB + 1);
       double x[2] = {0.0, 0.0}, mb[3] = {0.0, 0.0, 0.0};
+      if constexpr (WIDE) {
+        const GAS double *l0 = glat + lo.lam + k0 * NBX, *l1 = glat + lo.lam + min(k0 + 1, qh - 1) * NBX;
 #pragma unroll 8
-      for (int m = 0; m < NB; m++) {
-        const double g = Gc[m];
-        x[0] += g * l0[m]; x[1] += g * l1[m];
-        const double d = s_P[m] - u, hv = s_hQ[m] * g;
-        mb[0] += hv; mb[1] += hv * d; mb[2] += hv * d * d;
+        for (int m = 0; m < NBX; m++) {
+          const double g = Gc[m];
+          x[0] += g * l0[m]; x[1] += g * l1[m];
+          const double d = s_P[m] - u, hv = s_hQ[m] * g;
+          mb[0] += hv; mb[1] += hv * d; mb[2] += hv * d * d;
+        }
+      } else {
+        const double *l0 = s_lam + k0 * (NB + 1), *l1 = s_lam + min(k0 + 1, qh - 1) * (NB + 1);
+#pragma unroll 8
+        for (int m = 0; m < NB; m++) {
+          const double g = Gc[m];
+          x[0] += g * l0[m]; x[1] += g * l1[m];
+          const double d = s_P[m] - u, hv = s_hQ[m] * g;
+          mb[0] += hv; mb[1] += hv * d; mb[2] += hv * d * d;
+        }
       }
       const double sg = h ? -1.0 : 1.0, n = s_c[cl][0];
       const size_t i = (size_t)c0 + cl;
@@ -1148,17 +1169,25 @@ hipError_t launch_nbar(int prec, const CaseDev *cases, const int *map, int nbloc
 }
 
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
-                        hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                        bool wide, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
   const int4 *m = (const int4 *)map;
   // small maps are latency-bound: twice the threads per block shorten the
   // per-phase work of each thread; large maps keep more blocks resident
+  hipEvent_t e1s = wide ? nullptr : e1;
   if (nblocks <= TABLE_WIDE_MAX) {
-    if (prec == 0) launch_k(k_table<double, 512>, dim3(nblocks), dim3(512), 0, s, e0, e1, cases, m, mode, gin);
-    else launch_k(k_table<float, 512>, dim3(nblocks), dim3(512), 0, s, e0, e1, cases, m, mode, gin);
+    if (prec == 0) launch_k(k_table<double, 512, false>, dim3(nblocks), dim3(512), 0, s, e0, e1s, cases, m, mode, gin);
+    else launch_k(k_table<float, 512, false>, dim3(nblocks), dim3(512), 0, s, e0, e1s, cases, m, mode, gin);
   } else {
-    if (prec == 0) launch_k(k_table<double, 256>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
-    else launch_k(k_table<float, 256>, dim3(nblocks), dim3(256), 0, s, e0, e1, cases, m, mode, gin);
+    if (prec == 0) launch_k(k_table<double, 256, false>, dim3(nblocks), dim3(256), 0, s, e0, e1s, cases, m, mode, gin);
+    else launch_k(k_table<float, 256, false>, dim3(nblocks), dim3(256), 0, s, e0, e1s, cases, m, mode, gin);
+  }
+  // orders above MAXQH: a second pass over the same map (after the first, so
+  // the wall fluxes are in place)
+  if (wide) {
+    if (prec == 0) hipLaunchKernelGGL((k_table<double, 512, true>), dim3(nblocks), dim3(512), 0, s, cases, m, mode, gin);
+    else hipLaunchKernelGGL((k_table<float, 512, true>), dim3(nblocks), dim3(512), 0, s, cases, m, mode, gin);
+    if (e1) { hipError_t r = hipEventRecord(e1, s); if (r != hipSuccess) return r; }
   }
   return hipGetLastError();
 }

@@ -9,6 +9,7 @@
 // weights are Christoffel numbers 1/sum_l h_l(p_k)^2.  Full-range
 // Gauss-Hermite rules (App. A) use the known Jacobi matrix of the normal
 // density (alpha_l = sqrt(l), beta = 0) with the same eigen/weight route.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -43,9 +44,13 @@ static void gauss_legendre(int n, std::vector<ld> &x, std::vector<ld> &w) {
 
 // recurrence coefficients of the orthonormal polynomials of the half-range
 // weight: p h_l = a[l+1] h_{l+1} + b[l] h_l + a[l] h_{l-1}, h_0 = 1/sqrt(mu0)
+// (composite Gauss-Legendre on [0, PMAX]: h_l^2 times the weight is below
+// 1e-100 of its mass beyond PMAX for every l <= L; the panels keep a few
+// half-oscillations of h_L each)
 static void half_range_recurrence(int L, std::vector<ld> &a, std::vector<ld> &b, ld &mu0) {
-  const int NP = 64, NG = 24;
-  const ld PMAX = 32.0L, pi = 3.141592653589793238462643383279502884L;
+  const bool high = L > 64;
+  const int NP = high ? 160 : 64, NG = 24;
+  const ld PMAX = high ? 64.0L : 32.0L, pi = 3.141592653589793238462643383279502884L;
   std::vector<ld> gx, gw;
   gauss_legendre(NG, gx, gw);
   std::vector<ld> X, W;
@@ -155,7 +160,7 @@ static double chi_cs(double eta) { return 0.5 * (2 - eta) / ((1 - eta) * (1 - et
 
 int validate(const fdlb_params &p, std::string &why, double *sigma, double *R) {
   if (!(p.nx >= 7)) { why = "nx must be >= 7"; return -1; }
-  if (p.qx_half < 1 || p.qx_half > MAXQH) { why = "qx_half must be in [1, 32]"; return -1; }
+  if (p.qx_half < 1 || p.qx_half > MAXQH_WIDE) { why = "qx_half must be in [1, 200]"; return -1; }
   if (p.qy < 2 || p.qy > MAXQY || p.qz < 2 || p.qz > MAXQY) { why = "qy, qz must be in [2, 8]"; return -1; }
   if (!(p.eta0 >= 0 && p.eta0 < 0.5)) { why = "eta0 must be in [0, 0.5)"; return -1; }
   if (p.kn <= 0 && p.eta0 > 0) { why = "Kn = infinity requires eta0 = 0"; return -1; }
@@ -189,17 +194,17 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   c.nxp = fslots(c.nx);
   c.sigma = sigma; c.R = R; c.Lc = 1.0 - sigma;
   c.chi0 = chi_cs(p.eta0);
-  const int Q = c.qh;
+  const int Q = c.qh, nb = base_nodes(Q);
   // lattice offsets
   LatOff &o = c.lo;
   int off = 0;
   // p_x .. H_z form one contiguous block in this order (the table kernel
   // stages it with a single linear copy)
   o.px = off; off += 2 * Q;
-  o.bP = off; off += NB;
-  o.bA = off; off += NB;
-  o.hQ = off; off += NB;
-  o.lam = off; off += Q * NB;
+  o.bP = off; off += nb;
+  o.bA = off; off += nb;
+  o.hQ = off; off += nb;
+  o.lam = off; off += Q * nb;
   o.ck = off; off += Q;
   o.Hy = off; off += c.qy * c.qy;
   o.Hz = off; off += c.qz * c.qz;
@@ -220,13 +225,13 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   c.lat.assign(off, 0.0);
   double *L = c.lat.data();
 
-  // half-range rule of order Q and the base rule of order NB
+  // half-range rule of order Q and the base rule of order nb
   std::vector<ld> a, b, xq, wq, xb, wb;
   ld mu0;
-  int Lmax = NB + 2;
+  int Lmax = std::max(nb, Q) + 2;
   half_range_recurrence(Lmax, a, b, mu0);
   gauss_rule(Q, a, b, mu0, xq, wq);
-  gauss_rule(NB, a, b, mu0, xb, wb);
+  gauss_rule(nb, a, b, mu0, xb, wb);
   c.wx.assign(2 * Q, 0);
   for (int k = 0; k < Q; k++) {
     L[o.px + k] = (double)xq[k]; L[o.px + Q + k] = -(double)xq[k];
@@ -240,7 +245,7 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     for (int l = 0; l <= Q; l++) hk[k][l] = h[l];
     L[o.ck + k] = (double)(1 / dh[Q]);
   }
-  for (int m = 0; m < NB; m++) {
+  for (int m = 0; m < nb; m++) {
     ortho_vals(xb[m], Q, a, b, mu0, hb.data());
     L[o.bP + m] = (double)xb[m];
     L[o.bA + m] = (double)(logl(wb[m]) + xb[m] * xb[m] / 2);
@@ -248,7 +253,7 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     for (int k = 0; k < Q; k++) {
       ld s = 0;
       for (int l = 0; l < Q; l++) s += hk[k][l] * hb[l];
-      L[o.lam + k * NB + m] = (double)(wq[k] * s);
+      L[o.lam + k * nb + m] = (double)(wq[k] * s);
     }
   }
   // full-range rules on y and z (normal density, alpha_l = sqrt(l), beta = 0)

@@ -1,0 +1,92 @@
+"""Half-range orders above 32: the wide table pass (an NB_WIDE = 144-node base
+rule, Lagrange rows read from global memory) that serves Q_x^h up to 200, the
+reference order of the quadrature convergence test (Sec. IV, Table tab:quad).
+
+Parity with the oracle runs where the oracle's projections are pinned
+(Q_x^h <= 48); above that, properties that hold at any order: the projected
+state reproduces the moments it was built from, and mass is conserved.
+"""
+import numpy as np
+import pytest
+
+import fdlb_inputs as I
+from tests.gpu_util import rel_moment_errors, seeded_state
+from tests.test_gpu_parity import TOL64, _compare, _pair
+
+pytestmark = pytest.mark.gpu
+
+
+def _solver(cfgs, **kw):
+    from paper_2308_15407_amd.solver import Solver
+    return Solver(cfgs, **kw)
+
+
+@pytest.mark.parametrize("flow,kw,prec", [("C2", dict(nx=40, qx_half=40), 0),
+                                          ("C3", dict(nx=36, qx_half=48, qy=4, qz=4), 0),
+                                          ("C1", dict(nx=24, qx_half=33), 0),
+                                          ("C2", dict(nx=40, qx_half=40), 1)])
+def test_wide_orders_match_oracle(flow, kw, prec):
+    cfg = dict(I.config(flow, **kw), precision=prec)
+    s, o = _pair(cfg, 40)
+    s.step(6)
+    o.step(6)
+    if prec == 0:
+        _compare(s, o, TOL64, "%s Q=%d" % (flow, kw["qx_half"]))
+    else:
+        err = rel_moment_errors(s.moments(0), o.moments())
+        print("%s Q=%d FP32" % (flow, kw["qx_half"]), {k: "%.1e" % v for k, v in err.items()}, flush=True)
+        for k in ("n", "uy", "T", "Pxy"):
+            assert err[k] < 1e-5, (k, err[k])
+        for k in ("ux", "qx"):
+            assert err[k] < 1e-4, (k, err[k])
+
+
+@pytest.mark.parametrize("Q", [64, 120, 200])
+def test_wide_projection_reproduces_the_fields(Q):
+    """A state set from fields (n, u_x, u_y, T, q_x, P_xy) is the projected
+    Grad-13-type distribution; its moments are the fields to rounding when
+    every axis resolves the cubic (Q_y = Q_z = 4).  Aliasing of the base rule
+    would show here first."""
+    nx = 48
+    s = _solver(dict(I.config("C2", nx=nx, qx_half=Q, qy=4, qz=4)))
+    fields = I.smooth_fields(50 + Q, nx, amp=0.08)
+    s.set_state(0, fields, None)
+    m = s.moments(0)
+    err = {"n": np.max(np.abs(m[0] - fields[0]) / fields[0]),
+           "ux": np.max(np.abs(m[1] - fields[1])), "uy": np.max(np.abs(m[2] - fields[2])),
+           "T": np.max(np.abs(m[3] - fields[3]) / fields[3]),
+           "qx": np.max(np.abs(m[4] - fields[4])), "Pxy": np.max(np.abs(m[7] - fields[5]))}
+    print("Q=%d" % Q, {k: "%.1e" % v for k, v in err.items()}, flush=True)
+    for k, v in err.items():
+        assert v < 1e-12, (k, v)
+
+
+def test_wide_order_200_conserves_mass_and_stays_finite():
+    nx = 40
+    cfg = I.config("C2", nx=nx, qx_half=200, qy=4, qz=4)
+    s = _solver(cfg)
+    fields, noise = seeded_state(61, nx, 2 * 200 * 16)
+    s.set_state(0, fields, noise)
+    m0 = s.mass(0)
+    s.step(200)
+    m = s.moments(0)
+    assert np.all(np.isfinite(m))
+    assert abs(s.mass(0) - m0) < 1e-13 * m0
+
+
+def test_batch_mixing_standard_and_wide_orders_matches_single_bitwise():
+    """The standard and wide table passes share the launch map; every case of
+    a mixed batch evolves exactly as it does alone."""
+    cfgs = [I.config("C2", nx=40, qx_half=8), I.config("C2", nx=45, qx_half=40),
+            I.config("C1", nx=30, qx_half=64, precision=1), I.config("C3", nx=33, qx_half=5, qy=5, qz=3)]
+    b = _solver(cfgs)
+    singles = [_solver(c) for c in cfgs]
+    for i, c in enumerate(cfgs):
+        K = 2 * c["qx_half"] * c["qy"] * c["qz"]
+        fields, noise = seeded_state(70 + i, c["nx"], K)
+        b.set_state(i, fields, noise)
+        singles[i].set_state(0, fields, noise)
+    b.step(23)
+    for i, s in enumerate(singles):
+        s.step(23)
+        assert np.array_equal(b.get_f(i), s.get_f(0)), i

@@ -1,5 +1,6 @@
 """The C-ABI library builds, loads, and exports every symbol of include/fdlb.h
 (host-side checks only; no device calls)."""
+import math
 import os
 import re
 
@@ -37,6 +38,9 @@ def test_validation_errors():
         F.fdlb_case_info(dict(I.BASE, kn=0.0, eta0=0.1))      # Kn = inf needs eta0 = 0
     with pytest.raises(F.FdlbError):
         F.fdlb_case_info(dict(I.BASE, qy=9))
+    with pytest.raises(F.FdlbError):
+        F.fdlb_case_info(dict(I.BASE, qx_half=201))               # above the wide tables
+    assert F.fdlb_case_info(dict(I.BASE, qx_half=200, qy=2, qz=2))["K"] == 1600
     with pytest.raises(F.FdlbError):
         F.fdlb_case_info(dict(I.BASE, chi_mode=2))                # unknown contact value
     with pytest.raises(F.FdlbError):
@@ -85,3 +89,33 @@ def test_sweep_batch_is_seeded_and_valid():
     assert {c["qx_half"] for c in a} == {4, 8, 12, 16}
     assert all(c["precision"] == 1 and c["qy"] == 4 and c["qz"] == 4 for c in a)
     assert {c["flow"] for c in a} == {0, 1, 2}
+
+
+@pytest.mark.parametrize("Q", [33, 40, 64, 100, 150, 200])
+def test_wide_half_range_rule_is_exact(Q):
+    """Orders above 32 (the wide tables): sum_k w_k p_k^s over the positive
+    x-nodes equals the half-range moment 2^((s-1)/2) Gamma((s+1)/2)/sqrt(2 pi)
+    of the weight exp(-p^2/2)/sqrt(2 pi) for every s < 2Q (Gauss exactness,
+    Sec. III.A.2).  Compared in log form (the moments reach 1e600)."""
+    from paper_2308_15407_amd import fdlb as F
+    px, _, _, w = F.fdlb_case_lattice(dict(I.BASE, qx_half=Q, qy=2, qz=2, nx=16))
+    p = px.reshape(2 * Q, -1)[:Q, 0]
+    wx = w.reshape(2 * Q, -1).sum(axis=1)[:Q]
+    assert np.all(p > 0) and np.all(np.diff(p) > 0) and np.all(wx > 0)
+    assert np.allclose(px.reshape(2 * Q, -1)[Q:, 0], -p, rtol=0, atol=0)
+    for s in range(2 * Q):
+        lg = (s - 1) / 2 * math.log(2) + math.lgamma((s + 1) / 2) - 0.5 * math.log(2 * math.pi)
+        ratio = np.sum(wx * np.exp(s * np.log(p) - lg))
+        assert abs(ratio - 1) < 5e-16 * (40 + s * math.log(p[-1])), (s, ratio)
+
+
+@pytest.mark.parametrize("Q", [40, 48])
+def test_wide_host_lattice_matches_oracle(Q):
+    """The wide rule (Stieltjes/Sturm/Christoffel on the finer discretisation)
+    against the oracle's roots of h_Q with the paper's weight formula."""
+    from paper_2308_15407_amd import fdlb as F
+    from oracle import oracle as O
+    px, _, _, w = F.fdlb_case_lattice(dict(I.BASE, qx_half=Q, qy=2, qz=2, nx=16))
+    p, ow = O.hr_rule(Q)
+    assert np.max(np.abs(px.reshape(2 * Q, -1)[:Q, 0] - p)) < 1e-13
+    assert np.max(np.abs(w.reshape(2 * Q, -1).sum(axis=1)[:Q] - ow) / ow) < 1e-12

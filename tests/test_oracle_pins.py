@@ -19,7 +19,7 @@ import fdlb_inputs as I
 # --------------------------------------------------------------------------
 # P1  quadratures (Sec. III.A.2 half-range, App. A full-range)
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("Q", [1, 2, 4, 8, 12, 16, 20, 24, 28, 31, 32])
+@pytest.mark.parametrize("Q", [1, 2, 4, 8, 12, 16, 20, 24, 28, 31, 32, 40, 48])
 def test_half_range_rule_exact_moments(Q):
     """Sum_k w_k p_k^s equals the half-range moment of exp(-p^2/2)/sqrt(2 pi)
     for every s < 2Q (Gauss exactness, which fixes the rule uniquely)."""
@@ -68,7 +68,7 @@ def _half_moment(u, T, a, s, side):
     return integrate.quad(f, -np.inf, 0, epsabs=1e-15, epsrel=1e-13, limit=200)[0]
 
 
-@pytest.mark.parametrize("Q", [4, 8, 16, 24, 32])
+@pytest.mark.parametrize("Q", [4, 8, 16, 24, 32, 40, 48])
 @pytest.mark.parametrize("u,T", [(0.0, 1.0), (0.3, 1.2), (-0.4, 0.8), (0.1, 1.6)])
 def test_half_range_projection_recovers_half_moments(Q, u, T):
     """Sum over each half of X_a[k] p_k^s equals the exact half-range moment of
