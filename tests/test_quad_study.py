@@ -1,0 +1,77 @@
+"""Host logic of the quadrature convergence study (no GPU): the Knudsen
+number of (R, eta0), the grid, the error measure, the order selection, and the
+committed results."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_2308_15407_amd import mfr_study as M
+from paper_2308_15407_amd import quad_study as Q
+
+
+def test_kn_for_inverts_the_density_relation():
+    """Kn(R, eta0) and the flow-rate study's eta0(R, Kn) are inverse maps of
+    Kn = 1/(6 sqrt2 eta0 chi(eta0) R)."""
+    for R in Q.R_VALUES:
+        for eta0 in Q.ETA_VALUES:
+            kn = Q.kn_for(R, eta0)
+            old = M.ETA_MAX
+            try:
+                M.ETA_MAX = 0.45
+                assert M.eta0_for(R, kn) == pytest.approx(eta0, rel=1e-12)
+            finally:
+                M.ETA_MAX = old
+    # dilute limit: chi -> 1
+    assert Q.kn_for(10.0, 1e-9) * 6 * math.sqrt(2) * 1e-9 * 10 == pytest.approx(1.0, rel=1e-8)
+
+
+def test_grid_spacing_is_the_stated_fraction_of_sigma():
+    from paper_2308_15407_amd import fdlb as F
+    for R in Q.R_VALUES:
+        c = Q.case("couette", R, 0.1, 8)
+        x, jac = F.fdlb_case_grid(c)
+        sigma = F.fdlb_case_info(c)["sigma"]
+        dx = np.diff(x)
+        assert np.allclose(dx, sigma / Q.CELLS_PER_SIGMA, rtol=1e-12)
+        assert F.fdlb_case_info(c)["R"] == pytest.approx(R, rel=1e-12)
+
+
+def test_every_study_case_is_valid():
+    from paper_2308_15407_amd import fdlb as F
+    for flow in Q.FLOWS:
+        for q in (Q.Q_SCAN[0], Q.Q_SCAN[-1], Q.Q_REF):
+            info = F.fdlb_case_info(Q.case(flow, 10.0, 0.2, q))
+            spec = Q.FLOWS[flow]["case"]
+            assert info["K"] == 2 * q * spec["qy"] * spec["qz"]
+
+
+def test_eps_and_q_min():
+    ref = np.array([0.0, 1.0, 2.0, 1.0])
+    assert Q.eps(ref + [0, 0.02, 0, 0], ref) == pytest.approx(0.01)
+    assert Q.eps(ref - [0.04, 0, 0, 0], ref) == pytest.approx(0.02)   # either sign counts
+    qs = [4, 6, 8, 10, 12]
+    assert Q.q_min(qs, [0.3, 0.005, 0.02, 0.004, 0.001]) == 10      # a later excursion resets
+    assert Q.q_min(qs, [0.3, 0.05, 0.009, 0.004, 0.001]) == 8
+    assert Q.q_min(qs, [0.3, 0.05, 0.02, 0.04, 0.011]) is None
+
+
+def test_committed_results_are_consistent():
+    path = Q.DEFAULT_OUT
+    if not os.path.exists(path):
+        pytest.skip("no committed results")
+    res = json.load(open(path))
+    assert res["q_ref"] == Q.Q_REF
+    for flow, d in res["flows"].items():
+        for R, by_eta in d["R"].items():
+            for eta0, e in by_eta.items():
+                assert e["q_min"] == Q.q_min(e["q"], e["eps"])
+                # a settled case has no spread; an averaged one reports its spread
+                for ok, sp in zip(e["converged"] + [e["converged_ref"]], e["spread"] + [e["spread_ref"]]):
+                    assert (ok and sp == 0.0) or (not ok and 0.0 < sp < Q.EPS_LIMIT), (flow, R, eta0, sp)
+                bound = [x + sp + e["spread_ref"] for x, sp in zip(e["eps"], e["spread"])]
+                assert e["q_min_bound"] == Q.q_min(e["q"], bound)
+                # the error falls by an order of magnitude or more over the scanned orders
+                assert e["eps"][-1] < 0.1 * e["eps"][0], (flow, R, eta0)
