@@ -87,6 +87,10 @@ def lib():
         L.orc_nbar.argtypes = [P, dp, dp]
         L.orc_nbar.restype = None
         L.orc_target.argtypes = [P, dp, dp, dp, C.POINTER(D)]
+        L.orc_create_reduced1d.restype = P
+        L.orc_set_weno_ideal.argtypes = [P, I]
+        L.orc_set_weno_ideal.restype = None
+        L.orc_create_reduced1d.argtypes = [C.POINTER(OrcParams)]
         _lib = L
     return _lib
 
@@ -98,9 +102,11 @@ DEFAULTS = dict(flow=0, kn=0.1, eta0=0.05, t_left=1.0, t_right=1.0, uy_left=0.0,
 
 
 class Oracle:
-    """One FDLB case on the CPU in FP64 (see fdlb_oracle.c)."""
+    """One FDLB case on the CPU in FP64 (see fdlb_oracle.c).  reduced1d=True
+    builds the paper's reduced 1D model of the Fourier flow instead: phi and
+    theta on the 2 qx_half x-nodes (rows 0..2Q-1 and 2Q..4Q-1 of get_f)."""
 
-    def __init__(self, **kw):
+    def __init__(self, reduced1d=False, **kw):
         d = dict(DEFAULTS)
         unknown = set(kw) - set(d)
         if unknown:
@@ -108,7 +114,8 @@ class Oracle:
         d.update(kw)
         self.params = d
         self._p = OrcParams(**d)
-        self._h = lib().orc_create(C.byref(self._p))
+        self.reduced1d = bool(reduced1d)
+        self._h = (lib().orc_create_reduced1d if reduced1d else lib().orc_create)(C.byref(self._p))
         if not self._h:
             raise ValueError("oracle rejected parameters %r" % d)
         self.nx = d["nx"]
@@ -144,6 +151,11 @@ class Oracle:
         else:
             noise = np.ascontiguousarray(noise, dtype=np.float64).reshape(self.K, self.nx)
             lib().orc_set_state(self._h, fields, noise.ctypes.data_as(C.c_void_p))
+
+    def set_weno_ideal(self, on=True):
+        """Advect with the ideal (linear) WENO weights: a switch for the
+        cross-check between the 3D lattice and the reduced model only."""
+        lib().orc_set_weno_ideal(self._h, 1 if on else 0)
 
     def step(self, n=1):
         lib().orc_step(self._h, int(n))

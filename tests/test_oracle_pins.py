@@ -486,3 +486,72 @@ def test_ret_chi_reduces_to_local_chi_in_the_dilute_limit():
     b = O.Oracle(**dict(base, chi_mode=1))
     a.step(20); b.step(20)
     assert np.max(np.abs(a.moments() - b.moments())) < 1e-9
+
+
+# --------------------------------------------------------------------------
+# P6  the reduced 1D model (Sec. II.B, 1D flows) against the 3D lattice
+# --------------------------------------------------------------------------
+def _reduced_pair(collision, eta0, kn, nx=24, qh=5):
+    cfg = dict(I.BASE, flow=I.FOURIER, nx=nx, qx_half=qh, qy=4, qz=4, t_left=0.8, t_right=1.3, t_init=1.0,
+               kn=kn, eta0=eta0, collision=collision, pr_fixed=0.6)
+    o3 = O.Oracle(**cfg)
+    o1 = O.Oracle(reduced1d=True, **cfg)
+    f = I.smooth_fields(7, nx, amp=0.08)
+    f[2] = 0.0
+    f[5] = 0.0
+    o3.set_state(f)
+    o1.set_state(f)
+    return o3, o1
+
+
+def _transverse_sums(o3, qh, nx):
+    px, py, pz, w = o3.lattice()
+    F = o3.get_f().reshape(2 * qh, 16, nx)
+    pyz2 = (py ** 2 + pz ** 2).reshape(2 * qh, 16)[0]
+    return F.sum(axis=1), np.einsum('kjx,j->kx', F, pyz2)
+
+
+@pytest.mark.parametrize("collision,eta0,kn", [(I.BGK, 0.1, 0.1), (I.SHAKHOV_DENSE, 0.2, 0.05),
+                                               (I.SHAKHOV_FIXED, 0.05, 0.5)])
+def test_reduced_1d_model_is_the_transverse_sum_of_the_3d_lattice(collision, eta0, kn):
+    """The paper's reduced phi/theta equations (eq:evolution_1D with the printed
+    phi^S, theta^S, J1^phi, J1^theta) against the 3D product lattice with
+    Q_y = Q_z = 4, where phi = sum over (p_y, p_z) of f and theta = the sum
+    weighted by p_y^2 + p_z^2.  Every step of the 3D evolution commutes with
+    these sums except the nonlinear WENO weights, so with the ideal weights
+    (a switch of the oracle's advection) the two agree to rounding over many
+    steps; with the nonlinear weights they agree to the weights' deviation."""
+    nx, qh = 24, 5
+    o3, o1 = _reduced_pair(collision, eta0, kn, nx, qh)
+    phi, theta = _transverse_sums(o3, qh, nx)
+    g = o1.get_f().reshape(2, 2 * qh, nx)
+    assert np.max(np.abs(phi - g[0])) < 1e-14 and np.max(np.abs(theta - g[1])) < 1e-14
+    o3.set_weno_ideal()
+    o1.set_weno_ideal()
+    o3.step(30)
+    o1.step(30)
+    phi, theta = _transverse_sums(o3, qh, nx)
+    g = o1.get_f().reshape(2, 2 * qh, nx)
+    assert np.max(np.abs(phi - g[0])) < 1e-13 * np.max(np.abs(g[0]))
+    assert np.max(np.abs(theta - g[1])) < 1e-13 * np.max(np.abs(g[1]))
+    m3, m1 = o3.moments(), o1.moments()
+    for q in (0, 1, 3, 4, 6):     # n, u_x, T, q_x, P_xx
+        assert np.max(np.abs(m3[q] - m1[q])) < 1e-13, q
+
+
+def test_reduced_1d_model_conserves_mass_and_keeps_the_wall_equilibrium():
+    """With the nonlinear weights: mass is conserved at the diffuse walls, and a
+    gas at rest at the walls' common temperature stays exactly as it is."""
+    o3, o1 = _reduced_pair(I.SHAKHOV_DENSE, 0.2, 0.05)
+    x, jac = o1.grid()
+    m0 = float(np.sum(o1.moments()[0] * jac))
+    o1.step(200)
+    assert abs(float(np.sum(o1.moments()[0] * jac)) - m0) < 1e-13 * m0
+    cfg = dict(I.BASE, flow=I.FOURIER, nx=20, qx_half=4, qy=4, qz=4, t_left=1.2, t_right=1.2, t_init=1.2,
+               kn=0.1, eta0=0.2, collision=I.SHAKHOV_DENSE)
+    o = O.Oracle(reduced1d=True, **cfg)
+    f0 = o.get_f()
+    o.step(100)
+    assert np.max(np.abs(o.get_f() - f0)) < 1e-12 * np.max(np.abs(f0))
+    with pytest.raises(ValueError):
+        O.Oracle(reduced1d=True, **dict(cfg, uy_left=0.1))
