@@ -6,7 +6,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfdlb.so")
-SOURCES = ["fdlb_kernels.hip", "fdlb_api.cpp", "lattice.cpp", "mlp_kernels.hip", "mlp_api.cpp"]
+SOURCES = ["fdlb_kernels.hip", "fdlb_api.cpp", "lattice.cpp", "r1_api.cpp", "mlp_kernels.hip", "mlp_api.cpp"]
 ARCH = os.environ.get("FDLB_OFFLOAD_ARCH", "gfx950")
 
 

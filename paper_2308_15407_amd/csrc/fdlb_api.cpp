@@ -25,6 +25,10 @@ static int fail(int code, const std::string &msg) {
   return code;
 }
 
+namespace fdlb {
+int api_fail(int code, const std::string &msg) { return fail(code, msg); }
+}  // namespace fdlb
+
 #define HIPCHK(expr)                                                                  \
   do {                                                                                \
     hipError_t e_ = (expr);                                                           \

@@ -92,6 +92,23 @@ struct CaseDev {
   double *noise;        // staging [K][nx] for set_state (may be unused)
 };
 
+// One case of the reduced 1D model (Sec. II.B, 1D flows): phi and theta on
+// the 2 qh x-nodes, rows [0, 2qh) and [2qh, 4qh) of [R][nx] arrays (R = 4 qh).
+constexpr int R1_TILE = 16;    // cells per block of the reduced stage kernel
+constexpr int R1_HALO = 6;     // moment halo (the one-sided wall stencils reach 6 cells)
+struct R1Dev {
+  int nx, qh, R;
+  int collision;
+  double pr_fixed, eta0, tau_pre, dt;
+  const double *lat;    // lattice constants of the case (px, base rule, lambda, c_k, FD weights)
+  LatOff lo;
+  const double *invdx;  // [nx] 1 / (cell width)
+  const double *gw;     // [2][R] wall phi/theta at n = 1 (left, right)
+  double wallD[2];      // sum over the emitted phi rows of p_x g^w (left, right)
+  double *f, *g1, *g2;  // [R][nx] f^n and the two RK stage states
+  double *mom;          // [FDLB_NMOM][nx]
+};
+
 // ---------------------------------------------------------------------------
 // projection formulas
 // ---------------------------------------------------------------------------

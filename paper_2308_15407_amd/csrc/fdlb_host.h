@@ -29,6 +29,8 @@ struct CaseHost {
 };
 
 int validate(const fdlb_params &p, std::string &why, double *sigma, double *R);
+// records msg as the library's last error and returns code
+int api_fail(int code, const std::string &msg);
 int build_case(const fdlb_params &p, CaseHost &c, std::string &why);
 
 // table-pass mode bits
@@ -43,6 +45,10 @@ enum {
 
 // kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
+// reduced 1D model: nsteps TVD-RK3 steps of every case (map: int2 {case, tile}
+// per block of R1_TILE cells), and the moments of case c into its mom array
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, long nsteps, hipStream_t s);
+hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
 // wide: the map may hold cases with qx_half > MAXQH (adds the wide pass)
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
                         bool wide, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);

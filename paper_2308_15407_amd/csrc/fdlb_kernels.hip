@@ -1273,4 +1273,249 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
   return hipGetLastError();
 }
 
+
+// ---------------------------------------------------------------------------
+// reduced 1D model (Sec. II.B, 1D flows): one fused kernel per RK stage
+// ---------------------------------------------------------------------------
+// A block owns R1_TILE cells of one case.  It stages phi and theta of its
+// cells and a halo of R1_HALO cells per side in LDS, and then, without going
+// back to memory: the moments (eq:macro1D) of every staged cell, the wall
+// densities (tiles at a wall), the closure and the targets of its cells
+// (phi^S + tau J1^phi and theta^S + tau J1^theta as polynomials in xi times
+// f_x^MB, each projected on the half-range lattice), and the update of all
+// 4 qh rows of its cells: WENO-5 advection with the diffuse-wall rules of the
+// 3D pass, relaxation and the TVD-RK3 combination (eq:rk3).  The rows are
+// few (4 qh <= 128), so the whole stage fits one pass over the data.
+template <int STAGE>
+__global__ void __launch_bounds__(256) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
+  const int2 bm = map[blockIdx.x];
+  const R1Dev &c = cases[bm.x];
+  constexpr int W = R1_TILE + 2 * R1_HALO, RMAX = 4 * MAXQH;
+  __shared__ double s_g[RMAX][W];
+  __shared__ double s_t[RMAX][R1_TILE];
+  __shared__ double s_G[R1_TILE][2][NB + 1];
+  __shared__ double s_m[4][W];    // n, u_x, T, q_x
+  __shared__ double s_l[3][W];    // ln n, ln chi, ln T
+  __shared__ double s_c[R1_TILE][12];
+  __shared__ double s_nw[2];
+  const int nx = c.nx, qh = c.qh, Q2 = 2 * qh, R = c.R;
+  const int c0 = bm.y * R1_TILE, own = min(R1_TILE, nx - c0);
+  const int tid = threadIdx.x;
+  const double *lat = c.lat;
+  const LatOff lo = c.lo;
+  const double *gin = STAGE == 1 ? c.f : (STAGE == 2 ? c.g1 : c.g2);
+  double *gout = STAGE == 1 ? c.g1 : (STAGE == 2 ? c.g2 : c.f);
+
+  for (int it = tid; it < R * W; it += blockDim.x) {
+    const int r = it / W, w = it - r * W, cell = c0 - R1_HALO + w;
+    s_g[r][w] = (cell >= 0 && cell < nx) ? gin[(size_t)r * nx + cell] : 0.0;
+  }
+  __syncthreads();
+
+  // moments of the staged cells; wall densities in the wall tiles
+  if (tid < W) {
+    const int cell = c0 - R1_HALO + tid;
+    if (cell >= 0 && cell < nx) {
+      double n = 0.0, jx = 0.0;
+      for (int k = 0; k < Q2; k++) { n += s_g[k][tid]; jx += lat[lo.px + k] * s_g[k][tid]; }
+      const double ux = jx / n;
+      double pxx = 0.0, th = 0.0, qx = 0.0;
+      for (int k = 0; k < Q2; k++) {
+        const double cx = lat[lo.px + k] - ux, ph = s_g[k][tid], tt = s_g[Q2 + k][tid];
+        pxx += cx * cx * ph; th += tt;
+        qx += cx * (0.5 * cx * cx * ph + 0.5 * tt);
+      }
+      const double T_ = (pxx + th) / (3.0 * n);
+      s_m[0][tid] = n; s_m[1][tid] = ux; s_m[2][tid] = T_; s_m[3][tid] = qx;
+      s_l[0][tid] = log(n); s_l[1][tid] = log(chi_cs(c.eta0 * n)); s_l[2][tid] = log(T_);
+    }
+  } else if (tid == 64 || tid == 128) {
+    // impenetrability: the incoming phi rows reach the wall face through the
+    // fully interior candidate; n_w makes the net mass flux vanish.  Every
+    // tile whose stencils reach a wall's ghosts (cells within 3 of it) takes
+    // that wall's density; the cells it needs are staged.
+    const int wall = tid == 64 ? 0 : 1;
+    const bool here = wall == 0 ? c0 < 3 : c0 + own + 2 >= nx;
+    if (here) {
+      double in = 0.0;
+      for (int k = 0; k < Q2; k++) {
+        const double p = lat[lo.px + k];
+        if ((wall == 0) != (p < 0.0)) continue;
+        const int w0 = wall == 0 ? R1_HALO : nx - 1 - c0 + R1_HALO;   // the wall cell
+        const int st = wall == 0 ? 1 : -1;                             // into the domain
+        const double v0 = s_g[k][w0 + 2 * st], v1 = s_g[k][w0 + st], v2 = s_g[k][w0];
+        in += p * (v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0));
+      }
+      s_nw[wall] = -in / c.wallD[wall];
+    }
+  }
+  __syncthreads();
+
+  // closure and the coefficients of the two target polynomials per owned cell
+  if (tid < own) {
+    const int i = c0 + tid, li = tid + R1_HALO;
+    double g[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      const double *src = q < 3 ? s_l[q] : s_m[1];
+      double d = 0.0;
+      if (i >= 3 && i <= nx - 4) {
+        d = (src[li + 1] - src[li - 1]) * 0.75 - (src[li + 2] - src[li - 2]) * 0.15 +
+            (src[li + 3] - src[li - 3]) * (1.0 / 60.0);
+      } else if (i < 3) {
+        for (int jj = 0; jj < 7; jj++) d += lat[lo.fdw + i * 7 + jj] * src[li - i + jj];
+      } else {
+        const int r = nx - 1 - i;
+        for (int jj = 0; jj < 7; jj++) d -= lat[lo.fdw + r * 7 + jj] * src[li + r - jj];
+      }
+      g[q] = d * c.invdx[i];
+    }
+    const double n = s_m[0][li], ux = s_m[1][li], T_ = s_m[2][li], qx = s_m[3][li];
+    const double eta = c.eta0 * n, chi = chi_cs(eta), brc = 4.0 * eta * chi;
+    double tau = 0.0, itau = 0.0;
+    if (c.tau_pre > 0.0) {
+      tau = c.tau_pre / (n * sqrt(T_)) *
+            (1.0 / chi + 3.2 * eta + 64.0 / 25.0 * (1.0 + 12.0 / M_PI) * eta * eta * chi);
+      itau = 1.0 / tau;
+    }
+    double Pr = 1.0;
+    if (c.collision == 1) Pr = c.pr_fixed;
+    else if (c.collision == 2)
+      Pr = 2.0 / 3.0 * (1.0 + 0.8 * brc + 4.0 / 25.0 * (1.0 + 12.0 / M_PI) * brc * brc) /
+           (1.0 + 1.2 * brc + 9.0 / 25.0 * (1.0 + 32.0 / (9.0 * M_PI)) * brc * brc);
+    // phi: 1 + s0 (xi^2/T - 3) xi q_x + tau J1^phi / f^MB; theta / (2T):
+    // 1 + s0 (xi^2/T - 1) xi q_x + tau J1^theta / (2T f^MB), s0 = (1-Pr)/(5 n T^2)
+    const double s0 = (1.0 - Pr) / (5.0 * n * T_ * T_), iT = 1.0 / T_;
+    double cp[4] = {1.0, -3.0 * s0 * qx, 0.0, s0 * qx * iT};
+    double ct[4] = {1.0, -s0 * qx, 0.0, s0 * qx * iT};
+    if (itau > 0.0 && brc > 0.0) {
+      const double A = -tau * brc, g1 = g[1] + 2.0 * g[0];   // dln chi + 2 dln rho
+      cp[0] -= A * 0.6 * g[3]; cp[1] += A * (g1 + 0.1 * g[2]); cp[2] += A * 0.6 * g[3] * iT; cp[3] += A * 0.3 * g[2] * iT;
+      ct[0] -= A * 0.2 * g[3]; ct[1] += A * (g1 + 0.7 * g[2]); ct[2] += A * 0.6 * g[3] * iT; ct[3] += A * 0.3 * g[2] * iT;
+    }
+    s_c[tid][0] = n; s_c[tid][1] = ux; s_c[tid][2] = T_; s_c[tid][3] = itau;
+#pragma unroll
+    for (int a = 0; a < 4; a++) { s_c[tid][4 + a] = cp[a]; s_c[tid][8 + a] = 2.0 * T_ * ct[a]; }
+  } else if (tid >= 64) {
+    // half-range base weights per owned cell and half
+    for (int it = tid - 64; it < own * 2 * NB; it += blockDim.x - 64) {
+      const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
+      const int w = cl + R1_HALO;
+      const double u = h == 0 ? s_m[1][w] : -s_m[1][w], T_ = s_m[2][w];
+      const double d = lat[lo.bP + m] - u;
+      s_G[cl][h][m] = exp(lat[lo.bA + m] - d * d / (2.0 * T_)) * rsqrt(T_);
+    }
+  }
+  __syncthreads();
+
+  // targets: X_a[k] = Proj[g (p - u)^a] at node k (both halves), then
+  // phi_t = n sum_a cp_a X_a and theta_t = n sum_a (2T ct_a) X_a
+  for (int it = tid; it < own * Q2; it += blockDim.x) {
+    const int cl = it % own, hk = it / own, h = hk / qh, k = hk - h * qh;
+    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
+    const double *Gc = s_G[cl][h];
+    const double *lk = lat + lo.lam + k * NB;
+    double x0 = 0.0, mb0 = 0.0, mb1 = 0.0, mb2 = 0.0;
+    for (int m = 0; m < NB; m++) {
+      const double gv = Gc[m], d = lat[lo.bP + m] - u, hv = lat[lo.hQ + m] * gv;
+      x0 += gv * lk[m];
+      mb0 += hv; mb1 += hv * d; mb2 += hv * d * d;
+    }
+    const double dk = lat[lo.px + k] - u, ck = lat[lo.ck + k], sg = h ? -1.0 : 1.0;
+    const double X[4] = {x0, sg * (dk * x0 + ck * mb0), dk * dk * x0 + ck * (dk * mb0 + mb1),
+                         sg * (dk * dk * dk * x0 + ck * (dk * dk * mb0 + dk * mb1 + mb2))};
+    double tp = 0.0, tt = 0.0;
+#pragma unroll
+    for (int a = 0; a < 4; a++) { tp += s_c[cl][4 + a] * X[a]; tt += s_c[cl][8 + a] * X[a]; }
+    const double n = s_c[cl][0];
+    s_t[h * qh + k][cl] = n * tp;
+    s_t[Q2 + h * qh + k][cl] = n * tt;
+  }
+  __syncthreads();
+
+  // advection, relaxation and the RK combination of every row of the owned cells
+  const double nwl = c0 < 3 ? s_nw[0] : 0.0, nwr = c0 + own + 2 >= nx ? s_nw[1] : 0.0;
+  for (int it = tid; it < own * R; it += blockDim.x) {
+    const int cl = it % own, r = it / own, i = c0 + cl;
+    const double p = lat[lo.px + (r % Q2)];
+    const double *row = s_g[r];
+    const double fwl = nwl * c.gw[r], fwr = nwr * c.gw[R + r];
+    // face j (left face of cell j) in the upwind frame, with the wall rules:
+    // emitted populations take n_w g^w at the wall face and as ghosts; at the
+    // first interior faces of an incoming population the candidates that
+    // would reach past the wall are dropped
+    auto face = [&](int j) -> double {
+      if (p > 0.0) {
+        if (j == 0) return fwl;
+        double v[5];
+#pragma unroll
+        for (int s = 0; s < 5; s++) {
+          const int cc = j - 3 + s;
+          v[s] = cc < 0 ? fwl : (cc >= nx ? 0.0 : row[cc - c0 + R1_HALO]);
+        }
+        const int mode = j == nx ? 2 : (j == nx - 1 ? 1 : 0);
+        return weno_face<double>(v[0], v[1], v[2], v[3], v[4], mode);
+      }
+      if (j == nx) return fwr;
+      double v[5];
+#pragma unroll
+      for (int s = 0; s < 5; s++) {
+        const int cc = j + 2 - s;
+        v[s] = cc >= nx ? fwr : (cc < 0 ? 0.0 : row[cc - c0 + R1_HALO]);
+      }
+      const int mode = j == 0 ? 2 : (j == 1 ? 1 : 0);
+      return weno_face<double>(v[0], v[1], v[2], v[3], v[4], mode);
+    };
+    const double cen = row[cl + R1_HALO];
+    const double L = (s_t[r][cl] - cen) * s_c[cl][3] - p * (face(i + 1) - face(i)) * c.invdx[i];
+    const double adv = cen + c.dt * L;
+    double o;
+    if (STAGE == 1) o = adv;
+    else {
+      const double fn = c.f[(size_t)r * nx + i];
+      o = STAGE == 2 ? 0.75 * fn + 0.25 * adv : fn * (1.0 / 3.0) + (2.0 / 3.0) * adv;
+    }
+    gout[(size_t)r * nx + i] = o;
+  }
+}
+
+// moments [FDLB_NMOM][nx] of the reduced state f^n: n, u_x, u_y = 0, T, q_x,
+// q_y = 0, P_xx, P_xy = 0, P_yy = P_zz = theta / 2 (y and z are equivalent)
+__global__ void k_r1_moments(const R1Dev *__restrict__ cases, int c_idx) {
+  const R1Dev &c = cases[c_idx];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.nx) return;
+  const int nx = c.nx, Q2 = 2 * c.qh;
+  const double *px = c.lat + c.lo.px;
+  double n = 0.0, jx = 0.0;
+  for (int k = 0; k < Q2; k++) { n += c.f[(size_t)k * nx + i]; jx += px[k] * c.f[(size_t)k * nx + i]; }
+  const double ux = jx / n;
+  double pxx = 0.0, th = 0.0, qx = 0.0;
+  for (int k = 0; k < Q2; k++) {
+    const double cx = px[k] - ux, ph = c.f[(size_t)k * nx + i], tt = c.f[(size_t)(Q2 + k) * nx + i];
+    pxx += cx * cx * ph; th += tt;
+    qx += cx * (0.5 * cx * cx * ph + 0.5 * tt);
+  }
+  double *mo = c.mom;
+  mo[i] = n; mo[nx + i] = ux; mo[2 * nx + i] = 0.0; mo[3 * nx + i] = (pxx + th) / (3.0 * n);
+  mo[4 * nx + i] = qx; mo[5 * nx + i] = 0.0; mo[6 * nx + i] = pxx; mo[7 * nx + i] = 0.0;
+  mo[8 * nx + i] = 0.5 * th; mo[9 * nx + i] = 0.5 * th;
+}
+
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, long nsteps, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  const int2 *m = (const int2 *)map;
+  for (long k = 0; k < nsteps; k++) {
+    hipLaunchKernelGGL(k_r1_stage<1>, dim3(nblocks), dim3(256), 0, s, cases, m);
+    hipLaunchKernelGGL(k_r1_stage<2>, dim3(nblocks), dim3(256), 0, s, cases, m);
+    hipLaunchKernelGGL(k_r1_stage<3>, dim3(nblocks), dim3(256), 0, s, cases, m);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s) {
+  hipLaunchKernelGGL(k_r1_moments, dim3((nx + 255) / 256), dim3(256), 0, s, cases, c);
+  return hipGetLastError();
+}
+
 }  // namespace fdlb

@@ -27,7 +27,9 @@ EXPORTS = ("fdlb_workspace_bytes", "fdlb_case_info", "fdlb_case_lattice", "fdlb_
            "fdlb_set_tiling", "fdlb_set_graph_steps", "fdlb_profile", "fdlb_copy_probe", "fdlb_destroy",
            "fdlb_last_error", "fdlb_mlp_workspace_bytes", "fdlb_mlp_init", "fdlb_mlp_num_params",
            "fdlb_mlp_set_params", "fdlb_mlp_get_params", "fdlb_mlp_forward", "fdlb_mlp_loss_grad",
-           "fdlb_mlp_train_step", "fdlb_mlp_gemm_bf16", "fdlb_mlp_destroy", "fdlb_mlp_last_error")
+           "fdlb_mlp_train_step", "fdlb_mlp_gemm_bf16", "fdlb_mlp_destroy", "fdlb_mlp_last_error",
+           "fdlb_r1_workspace_bytes", "fdlb_r1_init", "fdlb_r1_step", "fdlb_r1_moments", "fdlb_r1_set_state",
+           "fdlb_r1_get_f", "fdlb_r1_dt", "fdlb_r1_destroy")
 
 
 class FdlbError(RuntimeError):
@@ -122,9 +124,19 @@ def lib():
         L.fdlb_mlp_destroy.argtypes = [P]
         L.fdlb_mlp_destroy.restype = None
         L.fdlb_mlp_last_error.restype = C.c_char_p
+        L.fdlb_r1_workspace_bytes.restype = Z
+        L.fdlb_r1_workspace_bytes.argtypes = [pp, I]
+        L.fdlb_r1_init.argtypes = [pp, I, P, Z, P, C.POINTER(P)]
+        L.fdlb_r1_step.argtypes = [P, C.c_long]
+        L.fdlb_r1_moments.argtypes = [P, I, dp]
+        L.fdlb_r1_set_state.argtypes = [P, I, dp, dp]
+        L.fdlb_r1_get_f.argtypes = [P, I, dp]
+        L.fdlb_r1_dt.argtypes = [P, I, dp]
+        L.fdlb_r1_destroy.argtypes = [P]
+        L.fdlb_r1_destroy.restype = None
         for name in EXPORTS:
             if name not in ("fdlb_workspace_bytes", "fdlb_destroy", "fdlb_last_error", "fdlb_mlp_workspace_bytes",
-                            "fdlb_mlp_destroy", "fdlb_mlp_last_error"):
+                            "fdlb_mlp_destroy", "fdlb_mlp_last_error", "fdlb_r1_workspace_bytes", "fdlb_r1_destroy"):
                 getattr(L, name).restype = I
         _lib = L
     return _lib
@@ -359,3 +371,51 @@ def fdlb_mlp_gemm_bf16(a_ptr, b_ptr, c_ptr, M, N, K, sam, sak, sbk, sbn, ldc, st
 
 def fdlb_mlp_destroy(h):
     lib().fdlb_mlp_destroy(h)
+
+
+# ---- reduced 1D model (phi, theta on the x-nodes) ----------------------------
+def fdlb_r1_workspace_bytes(cases):
+    arr = _params_array(cases)
+    n = lib().fdlb_r1_workspace_bytes(arr, len(cases))
+    if n == 0:
+        raise FdlbError(FDLB_EINVAL, lib().fdlb_last_error().decode())
+    return n
+
+
+def fdlb_r1_init(cases, workspace_ptr, nbytes, stream_ptr):
+    arr = _params_array(cases)
+    h = C.c_void_p()
+    _chk(lib().fdlb_r1_init(arr, len(cases), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def fdlb_r1_step(h, nsteps):
+    _chk(lib().fdlb_r1_step(h, int(nsteps)))
+
+
+def fdlb_r1_moments(h, c, nx):
+    out = np.zeros((FDLB_NMOM, nx))
+    _chk(lib().fdlb_r1_moments(h, c, _dptr(out)))
+    return out
+
+
+def fdlb_r1_set_state(h, c, fields, noise=None):
+    fields = np.ascontiguousarray(fields, dtype=np.float64)
+    noise = None if noise is None else np.ascontiguousarray(noise, dtype=np.float64)
+    _chk(lib().fdlb_r1_set_state(h, c, _dptr(fields), _dptr(noise)))
+
+
+def fdlb_r1_get_f(h, c, rows, nx):
+    out = np.zeros((rows, nx))
+    _chk(lib().fdlb_r1_get_f(h, c, _dptr(out)))
+    return out
+
+
+def fdlb_r1_dt(h, c):
+    out = C.c_double()
+    _chk(lib().fdlb_r1_dt(h, c, C.byref(out)))
+    return out.value
+
+
+def fdlb_r1_destroy(h):
+    lib().fdlb_r1_destroy(h)

@@ -109,3 +109,57 @@ class Solver:
     def mass(self, c=0):
         x, jac = self.grid(c)
         return float(np.sum(self.moments(c)[0] * jac) * 2.0 / self.nx[c])
+
+
+class ReducedSolver:
+    """A batch of Fourier cases in the paper's reduced 1D form: phi and theta
+    on the 2 qx_half x-nodes (include/fdlb.h, fdlb_r1_*), FP64."""
+
+    def __init__(self, cases, device="cuda:0", stream=None):
+        if isinstance(cases, dict):
+            cases = [cases]
+        if not torch.cuda.is_available():
+            raise RuntimeError("the FDLB solver needs a HIP device (torch.cuda.is_available() is False)")
+        self.cases = [dict(c) for c in cases]
+        self.device = torch.device(device)
+        nbytes = F.fdlb_r1_workspace_bytes(self.cases)
+        with torch.cuda.device(self.device):
+            self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=self.device)
+            self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+            self.handle = F.fdlb_r1_init(self.cases, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
+        self.nx = [c["nx"] for c in self.cases]
+        self.rows = [4 * c["qx_half"] for c in self.cases]
+
+    @property
+    def ncases(self):
+        return len(self.cases)
+
+    def close(self):
+        if getattr(self, "handle", None):
+            F.fdlb_r1_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n=1):
+        F.fdlb_r1_step(self.handle, n)
+
+    def synchronize(self):
+        self.stream.synchronize()
+
+    def moments(self, c=0):
+        return F.fdlb_r1_moments(self.handle, c, self.nx[c])
+
+    def set_state(self, c, fields, noise=None):
+        F.fdlb_r1_set_state(self.handle, c, fields, noise)
+
+    def get_f(self, c=0):
+        """[4 qx_half][nx]: phi rows, then theta rows."""
+        return F.fdlb_r1_get_f(self.handle, c, self.rows[c], self.nx[c])
+
+    def dt(self, c=0):
+        return F.fdlb_r1_dt(self.handle, c)

@@ -1,0 +1,84 @@
+"""The reduced 1D model of the Fourier flow (phi and theta on the x-nodes,
+Sec. II.B) on the GPU (fdlb_r1_* through the C ABI) against the oracle's
+reduced model, FP64 at 1e-10 as for the 3D path."""
+import numpy as np
+import pytest
+
+import fdlb_inputs as I
+from oracle import oracle as O
+from tests.gpu_util import rel_moment_errors, seeded_state
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+
+
+def _fourier(**kw):
+    d = dict(I.BASE, flow=I.FOURIER, t_left=0.8, t_right=1.3, t_init=1.0)
+    d.update(kw)
+    return d
+
+
+def _pair(cfg, seed, eps=1e-3):
+    from paper_2308_15407_amd.solver import ReducedSolver
+    s = ReducedSolver(cfg)
+    o = O.Oracle(reduced1d=True, **{k: v for k, v in cfg.items() if k != "precision"})
+    fields, noise = seeded_state(seed, cfg["nx"], 4 * cfg["qx_half"], 0.05, eps)
+    fields[2] = 0.0
+    fields[5] = 0.0
+    s.set_state(0, fields, noise)
+    o.set_state(fields, noise)
+    return s, o
+
+
+def _compare(s, o, label, tol=TOL64):
+    err = rel_moment_errors(s.moments(0), o.moments())
+    f_g, f_o = s.get_f(0), o.get_f()
+    ferr = np.max(np.abs(f_g - f_o)) / np.max(np.abs(f_o))
+    print(label, "f err %.2e" % ferr, {k: "%.1e" % v for k, v in err.items() if k in ("n", "ux", "T", "qx", "Pxx")},
+          flush=True)
+    assert ferr < tol, (label, ferr)
+    for k in ("n", "ux", "T", "qx", "Pxx", "Pyy"):
+        assert err[k] < tol, (label, k, err[k])
+
+
+@pytest.mark.parametrize("cfg,steps", [
+    (_fourier(nx=40, qx_half=4, kn=0.1, eta0=0.1, collision=I.BGK), 10),
+    (_fourier(nx=37, qx_half=8, kn=0.05, eta0=0.2, collision=I.SHAKHOV_DENSE, grid=I.GRID_TANH, stretch=1.5), 25),
+    (_fourier(nx=7, qx_half=3, kn=0.0, eta0=0.0), 30),
+    (_fourier(nx=20, qx_half=32, kn=0.3, eta0=0.05, collision=I.SHAKHOV_FIXED, pr_fixed=0.6), 4),
+    # last tiles of 2 and 1 cells: the tile before takes the right wall's
+    # density too, since its stencils reach the wall's ghosts
+    (_fourier(nx=50, qx_half=6, kn=0.02, eta0=0.15, collision=I.SHAKHOV_DENSE, t_left=0.5, t_right=1.5), 40),
+    (_fourier(nx=49, qx_half=5, kn=0.05, eta0=0.1, collision=I.BGK), 20),
+])
+def test_reduced_model_matches_oracle(cfg, steps):
+    s, o = _pair(cfg, 80 + cfg["nx"])
+    _compare(s, o, "init nx=%d Q=%d" % (cfg["nx"], cfg["qx_half"]))
+    s.step(steps)
+    o.step(steps)
+    _compare(s, o, "%d steps nx=%d Q=%d" % (steps, cfg["nx"], cfg["qx_half"]))
+
+
+def test_reduced_batch_matches_single_bitwise_and_conserves_mass():
+    from paper_2308_15407_amd.solver import ReducedSolver
+    cfgs = [_fourier(nx=40, qx_half=4, kn=0.1, eta0=0.1), _fourier(nx=23, qx_half=9, kn=0.05, eta0=0.2,
+                                                                     collision=I.SHAKHOV_DENSE),
+            _fourier(nx=64, qx_half=5, kn=0.5, eta0=0.01, grid=I.GRID_TANH, stretch=1.2)]
+    b = ReducedSolver(cfgs)
+    singles = [ReducedSolver(c) for c in cfgs]
+    for i, c in enumerate(cfgs):
+        fields, noise = seeded_state(90 + i, c["nx"], 4 * c["qx_half"])
+        fields[2] = 0.0
+        b.set_state(i, fields, noise)
+        singles[i].set_state(0, fields, noise)
+    m0 = [b.moments(i)[0] for i in range(3)]
+    b.step(300)
+    for i, s in enumerate(singles):
+        s.step(300)
+        assert np.array_equal(b.get_f(i), s.get_f(0)), i
+    # mass (sum of n times the cell widths) is conserved at the diffuse walls
+    from paper_2308_15407_amd import fdlb as F
+    for i, c in enumerate(cfgs):
+        x, jac = F.fdlb_case_grid(c)
+        assert abs(np.sum(b.moments(i)[0] * jac) - np.sum(m0[i] * jac)) < 1e-13 * np.sum(m0[i] * jac), i

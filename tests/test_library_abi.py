@@ -119,3 +119,14 @@ def test_wide_host_lattice_matches_oracle(Q):
     p, ow = O.hr_rule(Q)
     assert np.max(np.abs(px.reshape(2 * Q, -1)[:Q, 0] - p)) < 1e-13
     assert np.max(np.abs(w.reshape(2 * Q, -1).sum(axis=1)[:Q] - ow) / ow) < 1e-12
+
+
+def test_reduced_model_validation():
+    """The reduced 1D model takes Fourier-type cases only (host-side checks)."""
+    from paper_2308_15407_amd import fdlb as F
+    ok = dict(I.BASE, nx=32, qx_half=8)
+    assert F.fdlb_r1_workspace_bytes([ok, dict(ok, qx_half=32)]) > 0
+    for bad in (dict(ok, uy_left=0.1), dict(ok, ay=1e-3), dict(ok, chi_mode=1), dict(ok, precision=1),
+                dict(ok, qx_half=33), dict(ok, nx=5)):
+        with pytest.raises(F.FdlbError):
+            F.fdlb_r1_workspace_bytes([bad])
