@@ -94,7 +94,7 @@ struct CaseDev {
 
 // One case of the reduced 1D model (Sec. II.B, 1D flows): phi and theta on
 // the 2 qh x-nodes, rows [0, 2qh) and [2qh, 4qh) of [R][nx] arrays (R = 4 qh).
-constexpr int R1_TILE = 16;    // cells per block of the reduced stage kernel
+constexpr int R1_TILE = 32;    // cells per block of the reduced stage kernel
 constexpr int R1_HALO = 6;     // moment halo (the one-sided wall stencils reach 6 cells)
 struct R1Dev {
   int nx, qh, R;

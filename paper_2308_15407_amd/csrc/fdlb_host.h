@@ -47,7 +47,8 @@ enum {
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
 // reduced 1D model: nsteps TVD-RK3 steps of every case (map: int2 {case, tile}
 // per block of R1_TILE cells), and the moments of case c into its mom array
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, long nsteps, hipStream_t s);
+// (rmax: the largest 4 qh of the cases on the map)
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, long nsteps, hipStream_t s);
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
 // wide: the map may hold cases with qx_half > MAXQH (adds the wide pass)
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,

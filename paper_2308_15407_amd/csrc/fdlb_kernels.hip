@@ -1285,19 +1285,23 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 // f_x^MB, each projected on the half-range lattice), and the update of all
 // 4 qh rows of its cells: WENO-5 advection with the diffuse-wall rules of the
 // 3D pass, relaxation and the TVD-RK3 combination (eq:rk3).  The rows are
-// few (4 qh <= 128), so the whole stage fits one pass over the data.
-template <int STAGE>
-__global__ void __launch_bounds__(256) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
+// few (4 qh <= 128), so the whole stage fits one pass over the data.  RM is
+// the largest row count of the launch (64: qh <= 16, else 128), which sizes
+// the LDS and so the blocks resident per CU.
+template <int STAGE, int RM>
+__global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
   const int2 bm = map[blockIdx.x];
   const R1Dev &c = cases[bm.x];
-  constexpr int W = R1_TILE + 2 * R1_HALO, RMAX = 4 * MAXQH;
-  __shared__ double s_g[RMAX][W];
-  __shared__ double s_t[RMAX][R1_TILE];
+  constexpr int W = R1_TILE + 2 * R1_HALO;
+  __shared__ double s_g[RM][W];
+  __shared__ double s_t[RM][R1_TILE];
   __shared__ double s_G[R1_TILE][2][NB + 1];
   __shared__ double s_m[4][W];    // n, u_x, T, q_x
   __shared__ double s_l[3][W];    // ln n, ln chi, ln T
   __shared__ double s_c[R1_TILE][12];
   __shared__ double s_nw[2];
+  __shared__ double s_lam[RM / 4][NB + 1];  // Lagrange rows (padded by one: bank spread)
+  __shared__ double s_bh[2][NB];            // base nodes P_m and h_Q(P_m)
   const int nx = c.nx, qh = c.qh, Q2 = 2 * qh, R = c.R;
   const int c0 = bm.y * R1_TILE, own = min(R1_TILE, nx - c0);
   const int tid = threadIdx.x;
@@ -1305,36 +1309,50 @@ __global__ void __launch_bounds__(256) k_r1_stage(const R1Dev *__restrict__ case
   const LatOff lo = c.lo;
   const double *gin = STAGE == 1 ? c.f : (STAGE == 2 ? c.g1 : c.g2);
   double *gout = STAGE == 1 ? c.g1 : (STAGE == 2 ? c.g2 : c.f);
+  constexpr int SW = 4, NS = R1_TILE / SW;   // update strips: 4 cells of one row
 
   for (int it = tid; it < R * W; it += blockDim.x) {
     const int r = it / W, w = it - r * W, cell = c0 - R1_HALO + w;
     s_g[r][w] = (cell >= 0 && cell < nx) ? gin[(size_t)r * nx + cell] : 0.0;
   }
+  for (int it = tid; it < qh * NB; it += blockDim.x) s_lam[it / NB][it % NB] = lat[lo.lam + it];
+  for (int it = tid; it < NB; it += blockDim.x) { s_bh[0][it] = lat[lo.bP + it]; s_bh[1][it] = lat[lo.hQ + it]; }
   __syncthreads();
 
-  // moments of the staged cells; wall densities in the wall tiles
-  if (tid < W) {
-    const int cell = c0 - R1_HALO + tid;
-    if (cell >= 0 && cell < nx) {
-      double n = 0.0, jx = 0.0;
-      for (int k = 0; k < Q2; k++) { n += s_g[k][tid]; jx += lat[lo.px + k] * s_g[k][tid]; }
-      const double ux = jx / n;
-      double pxx = 0.0, th = 0.0, qx = 0.0;
-      for (int k = 0; k < Q2; k++) {
-        const double cx = lat[lo.px + k] - ux, ph = s_g[k][tid], tt = s_g[Q2 + k][tid];
+  // moments of the staged cells (8 lanes per cell, each summing every 8th
+  // node, then a butterfly over the 8 lanes); wall densities in the wall tiles
+  static_assert(8 * W <= 448, "moment lanes stay below the wall threads");
+  if (tid < 8 * W) {
+    const int wc = tid >> 3, sub = tid & 7, cell = c0 - R1_HALO + wc;
+    const bool live = cell >= 0 && cell < nx;   // uniform over the 8 lanes of a cell
+    double n = 0.0, jx = 0.0;
+    if (live)
+      for (int k = sub; k < Q2; k += 8) { n += s_g[k][wc]; jx += lat[lo.px + k] * s_g[k][wc]; }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) { n += __shfl_xor(n, off, 64); jx += __shfl_xor(jx, off, 64); }
+    const double ux = live ? jx / n : 0.0;
+    double pxx = 0.0, th = 0.0, qx = 0.0;
+    if (live)
+      for (int k = sub; k < Q2; k += 8) {
+        const double cx = lat[lo.px + k] - ux, ph = s_g[k][wc], tt = s_g[Q2 + k][wc];
         pxx += cx * cx * ph; th += tt;
         qx += cx * (0.5 * cx * cx * ph + 0.5 * tt);
       }
-      const double T_ = (pxx + th) / (3.0 * n);
-      s_m[0][tid] = n; s_m[1][tid] = ux; s_m[2][tid] = T_; s_m[3][tid] = qx;
-      s_l[0][tid] = log(n); s_l[1][tid] = log(chi_cs(c.eta0 * n)); s_l[2][tid] = log(T_);
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      pxx += __shfl_xor(pxx, off, 64); th += __shfl_xor(th, off, 64); qx += __shfl_xor(qx, off, 64);
     }
-  } else if (tid == 64 || tid == 128) {
+    if (live && sub == 0) {
+      const double T_ = (pxx + th) / (3.0 * n);
+      s_m[0][wc] = n; s_m[1][wc] = ux; s_m[2][wc] = T_; s_m[3][wc] = qx;
+      s_l[0][wc] = log(n); s_l[1][wc] = log(chi_cs(c.eta0 * n)); s_l[2][wc] = log(T_);
+    }
+  } else if (tid == 448 || tid == 480) {
     // impenetrability: the incoming phi rows reach the wall face through the
     // fully interior candidate; n_w makes the net mass flux vanish.  Every
     // tile whose stencils reach a wall's ghosts (cells within 3 of it) takes
     // that wall's density; the cells it needs are staged.
-    const int wall = tid == 64 ? 0 : 1;
+    const int wall = tid == 448 ? 0 : 1;
     const bool here = wall == 0 ? c0 < 3 : c0 + own + 2 >= nx;
     if (here) {
       double in = 0.0;
@@ -1402,80 +1420,110 @@ __global__ void __launch_bounds__(256) k_r1_stage(const R1Dev *__restrict__ case
       const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
       const int w = cl + R1_HALO;
       const double u = h == 0 ? s_m[1][w] : -s_m[1][w], T_ = s_m[2][w];
-      const double d = lat[lo.bP + m] - u;
+      const double d = s_bh[0][m] - u;
       s_G[cl][h][m] = exp(lat[lo.bA + m] - d * d / (2.0 * T_)) * rsqrt(T_);
     }
   }
   __syncthreads();
 
   // targets: X_a[k] = Proj[g (p - u)^a] at node k (both halves), then
-  // phi_t = n sum_a cp_a X_a and theta_t = n sum_a (2T ct_a) X_a
-  for (int it = tid; it < own * Q2; it += blockDim.x) {
-    const int cl = it % own, hk = it / own, h = hk / qh, k = hk - h * qh;
+  // phi_t = n sum_a cp_a X_a and theta_t = n sum_a (2T ct_a) X_a; an item is
+  // one cell and half and a pair of nodes, which share the base-weight reads
+  const int npair = (qh + 1) / 2;
+  for (int it = tid; it < own * 2 * npair; it += blockDim.x) {
+    const int cl = it % own, hk = it / own, h = hk / npair, k0 = 2 * (hk - h * npair);
+    const int k1 = min(k0 + 1, qh - 1);
     const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
     const double *Gc = s_G[cl][h];
-    const double *lk = lat + lo.lam + k * NB;
-    double x0 = 0.0, mb0 = 0.0, mb1 = 0.0, mb2 = 0.0;
+    const double *l0 = s_lam[k0], *l1 = s_lam[k1];
+    double x0a = 0.0, x0b = 0.0, mb0 = 0.0, mb1 = 0.0, mb2 = 0.0;
+#pragma unroll 8
     for (int m = 0; m < NB; m++) {
-      const double gv = Gc[m], d = lat[lo.bP + m] - u, hv = lat[lo.hQ + m] * gv;
-      x0 += gv * lk[m];
+      const double gv = Gc[m], d = s_bh[0][m] - u, hv = s_bh[1][m] * gv;
+      x0a += gv * l0[m]; x0b += gv * l1[m];
       mb0 += hv; mb1 += hv * d; mb2 += hv * d * d;
     }
-    const double dk = lat[lo.px + k] - u, ck = lat[lo.ck + k], sg = h ? -1.0 : 1.0;
-    const double X[4] = {x0, sg * (dk * x0 + ck * mb0), dk * dk * x0 + ck * (dk * mb0 + mb1),
-                         sg * (dk * dk * dk * x0 + ck * (dk * dk * mb0 + dk * mb1 + mb2))};
-    double tp = 0.0, tt = 0.0;
+    const double sg = h ? -1.0 : 1.0, n = s_c[cl][0];
 #pragma unroll
-    for (int a = 0; a < 4; a++) { tp += s_c[cl][4 + a] * X[a]; tt += s_c[cl][8 + a] * X[a]; }
-    const double n = s_c[cl][0];
-    s_t[h * qh + k][cl] = n * tp;
-    s_t[Q2 + h * qh + k][cl] = n * tt;
+    for (int j = 0; j < 2; j++) {
+      const int k = k0 + j;
+      if (k >= qh) break;
+      const double x0 = j == 0 ? x0a : x0b;
+      const double dk = lat[lo.px + k] - u, ck = lat[lo.ck + k];
+      const double X[4] = {x0, sg * (dk * x0 + ck * mb0), dk * dk * x0 + ck * (dk * mb0 + mb1),
+                           sg * (dk * dk * dk * x0 + ck * (dk * dk * mb0 + dk * mb1 + mb2))};
+      double tp = 0.0, tt = 0.0;
+#pragma unroll
+      for (int a = 0; a < 4; a++) { tp += s_c[cl][4 + a] * X[a]; tt += s_c[cl][8 + a] * X[a]; }
+      s_t[h * qh + k][cl] = n * tp;
+      s_t[Q2 + h * qh + k][cl] = n * tt;
+    }
   }
   __syncthreads();
 
-  // advection, relaxation and the RK combination of every row of the owned cells
+  // advection, relaxation and the RK combination: a thread takes one row and
+  // a strip of 4 owned cells, reconstructing the strip's 5 faces once
   const double nwl = c0 < 3 ? s_nw[0] : 0.0, nwr = c0 + own + 2 >= nx ? s_nw[1] : 0.0;
-  for (int it = tid; it < own * R; it += blockDim.x) {
-    const int cl = it % own, r = it / own, i = c0 + cl;
+  for (int it = tid; it < R * NS; it += blockDim.x) {
+    const int r = it / NS, q = it - r * NS, cl0 = q * SW;
+    if (cl0 >= own) continue;
+    const int ncl = min(SW, own - cl0);
     const double p = lat[lo.px + (r % Q2)];
     const double *row = s_g[r];
     const double fwl = nwl * c.gw[r], fwr = nwr * c.gw[R + r];
     // face j (left face of cell j) in the upwind frame, with the wall rules:
     // emitted populations take n_w g^w at the wall face and as ghosts; at the
     // first interior faces of an incoming population the candidates that
-    // would reach past the wall are dropped
+    // would reach past the wall are dropped; faces clear of both walls use
+    // the branch-free interior form
     auto face = [&](int j) -> double {
       if (p > 0.0) {
+        if (j >= 3 && j <= nx - 2) {
+          const int b = j - c0 + R1_HALO;
+          return weno_face_interior<double>(row[b - 3], row[b - 2], row[b - 1], row[b], row[b + 1]);
+        }
         if (j == 0) return fwl;
         double v[5];
 #pragma unroll
-        for (int s = 0; s < 5; s++) {
-          const int cc = j - 3 + s;
-          v[s] = cc < 0 ? fwl : (cc >= nx ? 0.0 : row[cc - c0 + R1_HALO]);
+        for (int s2 = 0; s2 < 5; s2++) {
+          const int cc = j - 3 + s2;
+          v[s2] = cc < 0 ? fwl : (cc >= nx ? 0.0 : row[cc - c0 + R1_HALO]);
         }
         const int mode = j == nx ? 2 : (j == nx - 1 ? 1 : 0);
         return weno_face<double>(v[0], v[1], v[2], v[3], v[4], mode);
       }
+      if (j >= 2 && j <= nx - 3) {
+        const int b = j - c0 + R1_HALO;
+        return weno_face_interior<double>(row[b + 2], row[b + 1], row[b], row[b - 1], row[b - 2]);
+      }
       if (j == nx) return fwr;
       double v[5];
 #pragma unroll
-      for (int s = 0; s < 5; s++) {
-        const int cc = j + 2 - s;
-        v[s] = cc >= nx ? fwr : (cc < 0 ? 0.0 : row[cc - c0 + R1_HALO]);
+      for (int s2 = 0; s2 < 5; s2++) {
+        const int cc = j + 2 - s2;
+        v[s2] = cc >= nx ? fwr : (cc < 0 ? 0.0 : row[cc - c0 + R1_HALO]);
       }
       const int mode = j == 0 ? 2 : (j == 1 ? 1 : 0);
       return weno_face<double>(v[0], v[1], v[2], v[3], v[4], mode);
     };
-    const double cen = row[cl + R1_HALO];
-    const double L = (s_t[r][cl] - cen) * s_c[cl][3] - p * (face(i + 1) - face(i)) * c.invdx[i];
-    const double adv = cen + c.dt * L;
-    double o;
-    if (STAGE == 1) o = adv;
-    else {
-      const double fn = c.f[(size_t)r * nx + i];
-      o = STAGE == 2 ? 0.75 * fn + 0.25 * adv : fn * (1.0 / 3.0) + (2.0 / 3.0) * adv;
+    double fl = face(c0 + cl0);
+#pragma unroll
+    for (int u = 0; u < SW; u++) {
+      if (u >= ncl) break;
+      const int cl = cl0 + u, i = c0 + cl;
+      const double fr = face(i + 1);
+      const double cen = row[cl + R1_HALO];
+      const double L = (s_t[r][cl] - cen) * s_c[cl][3] - p * (fr - fl) * c.invdx[i];
+      const double adv = cen + c.dt * L;
+      double o;
+      if (STAGE == 1) o = adv;
+      else {
+        const double fn = c.f[(size_t)r * nx + i];
+        o = STAGE == 2 ? 0.75 * fn + 0.25 * adv : fn * (1.0 / 3.0) + (2.0 / 3.0) * adv;
+      }
+      gout[(size_t)r * nx + i] = o;
+      fl = fr;
     }
-    gout[(size_t)r * nx + i] = o;
   }
 }
 
@@ -1502,14 +1550,21 @@ __global__ void k_r1_moments(const R1Dev *__restrict__ cases, int c_idx) {
   mo[8 * nx + i] = 0.5 * th; mo[9 * nx + i] = 0.5 * th;
 }
 
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, long nsteps, hipStream_t s) {
-  if (nblocks <= 0) return hipSuccess;
-  const int2 *m = (const int2 *)map;
+template <int RM>
+static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++) {
-    hipLaunchKernelGGL(k_r1_stage<1>, dim3(nblocks), dim3(256), 0, s, cases, m);
-    hipLaunchKernelGGL(k_r1_stage<2>, dim3(nblocks), dim3(256), 0, s, cases, m);
-    hipLaunchKernelGGL(k_r1_stage<3>, dim3(nblocks), dim3(256), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<1, RM>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<2, RM>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<3, RM>), dim3(nblocks), dim3(512), 0, s, cases, m);
   }
+}
+
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, long nsteps, hipStream_t s) {
+  if (nblocks <= 0) return hipSuccess;
+  if (rmax > 4 * MAXQH) return hipErrorInvalidValue;
+  const int2 *m = (const int2 *)map;
+  if (rmax <= 64) r1_steps<64>(cases, m, nblocks, nsteps, s);
+  else r1_steps<4 * MAXQH>(cases, m, nblocks, nsteps, s);
   return hipGetLastError();
 }
 

@@ -5,6 +5,7 @@
 // 3D path; the y and z velocity sets are not used.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -28,6 +29,7 @@ struct fdlb_r1_ctx {
   R1Dev *d_cases = nullptr;
   int *d_map = nullptr;
   int nmap = 0;
+  int rmax = 0;    // the largest row count (4 qx_half) of the cases
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -113,6 +115,7 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
     std::string why;
     if (r1_case(cases[i], c, why)) return bail(api_fail(FDLB_EINVAL, why));
     const int nx = c.nx, Q = c.qh, Q2 = 2 * Q, R = 4 * Q;
+    h->rmax = std::max(h->rmax, R);
     R1Dev &d = h->hdev[i];
     memset(&d, 0, sizeof(d));
     d.nx = nx; d.qh = Q; d.R = R;
@@ -164,7 +167,7 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
 
 extern "C" int fdlb_r1_step(fdlb_r1_handle h, long nsteps) {
   if (!h || nsteps < 0) return api_fail(FDLB_EINVAL, "null handle or negative step count");
-  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, nsteps, h->stream));
+  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, nsteps, h->stream));
   return FDLB_OK;
 }
 

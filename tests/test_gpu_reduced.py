@@ -47,10 +47,11 @@ def _compare(s, o, label, tol=TOL64):
     (_fourier(nx=37, qx_half=8, kn=0.05, eta0=0.2, collision=I.SHAKHOV_DENSE, grid=I.GRID_TANH, stretch=1.5), 25),
     (_fourier(nx=7, qx_half=3, kn=0.0, eta0=0.0), 30),
     (_fourier(nx=20, qx_half=32, kn=0.3, eta0=0.05, collision=I.SHAKHOV_FIXED, pr_fixed=0.6), 4),
-    # last tiles of 2 and 1 cells: the tile before takes the right wall's
-    # density too, since its stencils reach the wall's ghosts
-    (_fourier(nx=50, qx_half=6, kn=0.02, eta0=0.15, collision=I.SHAKHOV_DENSE, t_left=0.5, t_right=1.5), 40),
-    (_fourier(nx=49, qx_half=5, kn=0.05, eta0=0.1, collision=I.BGK), 20),
+    # last tiles (of 32 cells) holding 2 and 1 cells: the tile before takes the
+    # right wall's density too, since its stencils reach the wall's ghosts
+    (_fourier(nx=66, qx_half=6, kn=0.02, eta0=0.15, collision=I.SHAKHOV_DENSE, t_left=0.5, t_right=1.5), 40),
+    (_fourier(nx=65, qx_half=5, kn=0.05, eta0=0.1, collision=I.BGK), 20),
+    (_fourier(nx=100, qx_half=20, kn=0.1, eta0=0.1, collision=I.SHAKHOV_DENSE), 8),
 ])
 def test_reduced_model_matches_oracle(cfg, steps):
     s, o = _pair(cfg, 80 + cfg["nx"])
