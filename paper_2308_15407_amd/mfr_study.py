@@ -18,8 +18,11 @@ case counts as steady when its residual is below tol or its flow rate changed
 by less than RTOL (relative) over the last chunk of steps.
 
     python -m paper_2308_15407_amd.mfr_study run [--out PATH]
+    python -m paper_2308_15407_amd.mfr_study qscan [--out PATH]
 
-writes {"R": {...: {"kn": [...], "eta0": [...], "mfr": [...], "steps": [...]}}}.
+run writes {"R": {...: {"kn": [...], "eta0": [...], "mfr": [...], "steps": [...]}}};
+qscan (the dependence on the half-range order, the figure's panel (b)) writes
+{"R": R_QSCAN, "Q": {...: {"kn": [...], "mfr": [...], "steps": [...]}}}.
 """
 import argparse
 import json
@@ -33,6 +36,7 @@ import fdlb_inputs as I
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "mfr_results.json")
+DEFAULT_QSCAN_OUT = os.path.join(HERE, "mfr_qscan_results.json")
 
 R_VALUES = (2.0, 5.0, 10.0, 20.0)
 KN_VALUES = tuple(float(v) for v in np.round(np.logspace(-2, math.log10(2.0), 12), 5))
@@ -83,16 +87,12 @@ def mfr(solver, i):
 RTOL = 1e-7
 
 
-def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print):
+def settle(cfgs, tol=1e-10, max_steps=600000, chunk=25000, log=print):
+    """Step one batch until every case is steady (residual below tol, or flow
+    rate changed by at most RTOL over a chunk) or max_steps; returns the flow
+    rates, the steps at which each case settled (0 if never), the settled
+    mask, the residuals and the wall time."""
     from .solver import Solver
-    specs, cfgs = [], []
-    for R in R_VALUES:
-        for kn in KN_VALUES:
-            c = case(R, kn)
-            if c is not None:
-                specs.append((R, kn, c["eta0"]))
-                cfgs.append(c)
-    log("%d cases" % len(cfgs))
     s = Solver(cfgs, graph_steps=100)
     t0 = time.perf_counter()
     nc = len(cfgs)
@@ -116,6 +116,19 @@ def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print):
         log("  %d steps: %d of %d settled (%.1f s)" % (k, int(np.sum(done)), nc, time.perf_counter() - t0))
     wall = time.perf_counter() - t0
     log("finished in %.1f s" % wall)
+    return m, steps, done, res, wall
+
+
+def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print):
+    specs, cfgs = [], []
+    for R in R_VALUES:
+        for kn in KN_VALUES:
+            c = case(R, kn)
+            if c is not None:
+                specs.append((R, kn, c["eta0"]))
+                cfgs.append(c)
+    log("%d cases" % len(cfgs))
+    m, steps, done, res, wall = settle(cfgs, tol, max_steps, chunk, log)
     result = {"tol": tol, "rtol_mfr": RTOL, "chunk": chunk, "ay": AY, "eta_max": ETA_MAX,
               "wall_s": round(wall, 2), "R": {}}
     for i, (R, kn, eta0) in enumerate(specs):
@@ -129,14 +142,48 @@ def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print):
     return result
 
 
+# the order dependence (panel (b)): one confinement ratio, Kn up to the
+# free-molecular side of the Knudsen minimum, half-range orders up to 100
+R_QSCAN = 10.0
+KN_QSCAN = tuple(float(v) for v in np.round(np.logspace(-2, 1, 13), 5))
+Q_QSCAN = (8, 16, 32, 64, 100)
+
+
+def run_qscan(out=DEFAULT_QSCAN_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print):
+    specs, cfgs = [], []
+    for q in Q_QSCAN:
+        for kn in KN_QSCAN:
+            c = case(R_QSCAN, kn, qx_half=q)
+            if c is not None:
+                specs.append((q, kn))
+                cfgs.append(c)
+    log("%d cases" % len(cfgs))
+    m, steps, done, res, wall = settle(cfgs, tol, max_steps, chunk, log)
+    result = {"tol": tol, "rtol_mfr": RTOL, "chunk": chunk, "ay": AY, "R": R_QSCAN, "wall_s": round(wall, 2),
+              "Q": {}}
+    for i, (q, kn) in enumerate(specs):
+        d = result["Q"].setdefault("%d" % q, {"kn": [], "mfr": [], "steps": [], "resid": []})
+        d["kn"].append(kn); d["mfr"].append(float(m[i]))
+        d["steps"].append(int(steps[i]) if done[i] else -1); d["resid"].append(float(res[i]))
+    for q, d in result["Q"].items():
+        log("Q=%s " % q + " ".join("%.3g:%.4f" % (kn, v) for kn, v in zip(d["kn"], d["mfr"])))
+    with open(out, "w") as f:
+        json.dump(result, f, indent=1)
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["run"])
-    ap.add_argument("--out", default=DEFAULT_OUT)
+    ap.add_argument("cmd", choices=["run", "qscan"])
+    ap.add_argument("--out", default=None)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-steps", type=int, default=600000)
     a = ap.parse_args()
-    run(a.out, a.tol, a.max_steps, log=lambda msg: print(msg, flush=True))
+    log = lambda msg: print(msg, flush=True)
+    if a.cmd == "run":
+        run(a.out or DEFAULT_OUT, a.tol, a.max_steps, log=log)
+    else:
+        run_qscan(a.out or DEFAULT_QSCAN_OUT, a.tol, a.max_steps, log=log)
 
 
 if __name__ == "__main__":
