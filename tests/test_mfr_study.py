@@ -5,6 +5,7 @@ import json
 import math
 
 import numpy as np
+import pytest
 
 from paper_2308_15407_amd import mfr_study as M
 
@@ -71,3 +72,26 @@ def test_committed_results_show_the_knudsen_minimum_only_for_wide_channels():
     kn, m = settled[10.0]
     imax = int(np.argmax(m))
     assert 0 < imax and kn[imax] < 0.2                      # slip-regime maximum
+
+
+def test_committed_order_scan_converges_in_q():
+    """The order dependence (the figure's panel (b)): every case settled; at
+    moderate Kn all orders agree to 0.5 %, and at the largest Kn the low orders
+    deviate while the highest two agree to 1e-3."""
+    import os
+    path = M.DEFAULT_QSCAN_OUT
+    if not os.path.exists(path):
+        pytest.skip("no committed order scan")
+    res = json.load(open(path))
+    qs = sorted(res["Q"], key=int)
+    ref = res["Q"][qs[-1]]
+    for q in qs:
+        d = res["Q"][q]
+        assert d["kn"] == ref["kn"]
+        assert all(s > 0 for s in d["steps"]), q
+        for kn, m, mr in zip(d["kn"], d["mfr"], ref["mfr"]):
+            if kn <= 1.0:
+                assert abs(m - mr) < 5e-3 * mr, (q, kn, m, mr)
+    last = [res["Q"][q]["mfr"][-1] for q in qs]
+    assert abs(last[-1] - last[-2]) < 1e-3 * last[-1]
+    assert abs(last[0] - last[-1]) > 10 * abs(last[-2] - last[-1])
