@@ -56,7 +56,8 @@ struct fdlb_ctx {
   size_t lds[4] = {0, 0, 0, 0};   // dynamic LDS bytes of each group's update launch
   int waves = 4;
   int kx_user = 0;
-  bool wide = false;          // some case has qx_half > MAXQH (wide table pass)
+  int tileT[4] = {CTILE, CTILE, CTILE, CTILE};   // cells per block of each group's table map
+  bool wideT[4] = {false, false, false, false};  // the group holds cases with qx_half > MAXQH
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -108,7 +109,7 @@ static size_t map_entries(const std::vector<CaseHost> &cs) {
   size_t n = 0;
   for (auto &c : cs) {
     const int nkx = 2 * c.qh;
-    n += (size_t)((c.nx + CTILE - 1) / CTILE + 2) + (size_t)((c.nx + UTILE - 1) / UTILE) * nkx +
+    n += (size_t)((c.nx + CTILE_SMALL - 1) / CTILE_SMALL + 2) + (size_t)((c.nx + UTILE - 1) / UTILE) * nkx +
          (size_t)((c.nx + NBAR_TILE - 1) / NBAR_TILE);
   }
   return 2 * n + 2 * 64;  // room for both precision groups and XCD padding
@@ -196,8 +197,21 @@ static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
   std::vector<int> mt[4], mu[4], mn[4];
   for (int G = 0; G < 4; G++) { h->lds[G] = update_lds_bytes(G >> 1, 1, 1, h->waves, false); h->lds_n[G] = 0; }
-  h->wide = false;
-  for (const CaseHost &c : h->cases) h->wide = h->wide || c.qh > MAXQH;
+  // table tile per group: small maps without wide cases take CTILE_SMALL cells per block
+  {
+    int blocks[4] = {0, 0, 0, 0};
+    bool gwide[4] = {false, false, false, false};
+    for (const CaseHost &c : h->cases) {
+      if (!c.active) continue;
+      const int P = c.prec * 2 + (c.p.ay != 0.0 ? 1 : 0);
+      blocks[P] += (c.nx + CTILE - 1) / CTILE + 2;
+      gwide[P] = gwide[P] || c.qh > MAXQH;
+    }
+    for (int G = 0; G < 4; G++) {
+      h->wideT[G] = gwide[G];
+      h->tileT[G] = (!gwide[G] && blocks[G] <= SMALL_TABLE_MAP) ? CTILE_SMALL : CTILE;
+    }
+  }
   for (size_t ci = 0; ci < h->cases.size(); ci++) {
     CaseHost &c = h->cases[ci];
     CaseDev &d = h->hdev[ci];
@@ -217,7 +231,7 @@ static int build_maps(fdlb_ctx *h) {
     if (!c.active) continue;
     const int P = c.prec * 2 + (force ? 1 : 0);
     h->lds[P] = std::max(h->lds[P], update_lds_bytes(c.prec, qyz, c.kxc, h->waves, d.tlds != 0));
-    const int nct = (c.nx + CTILE - 1) / CTILE, nut = (c.nx + UTILE - 1) / UTILE;
+    const int nct = (c.nx + h->tileT[P] - 1) / h->tileT[P], nut = (c.nx + UTILE - 1) / UTILE;
     for (int t = 0; t < nct; t++) { mt[P].insert(mt[P].end(), {(int)ci, t, 0, 0}); }
     mt[P].insert(mt[P].end(), {(int)ci, -1, 0, 0});
     mt[P].insert(mt[P].end(), {(int)ci, -2, 0, 0});
@@ -278,7 +292,7 @@ static int launch_group_steps(fdlb_ctx *h, int G, long nsteps, hipStream_t s) {
     for (int stage = 1; stage <= 3; stage++) {
       int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
       if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], s));
-      HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wide, s));
+      HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wideT[G], h->tileT[G], s));
       HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
     }
   return FDLB_OK;
@@ -317,7 +331,7 @@ static int launch_moments(fdlb_ctx *h, bool resid) {
   if (resid) HIPCHK(launch_zero_resid(h->d_cases, (int)h->cases.size(), h->stream));
   for (int G = 0; G < 4; G++)
     HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G],
-                        TM_PARTIALS | TM_WRITE_MOM | (resid ? TM_RESID : 0), 0, h->wide, h->stream));
+                        TM_PARTIALS | TM_WRITE_MOM | (resid ? TM_RESID : 0), 0, h->wideT[G], h->tileT[G], h->stream));
   return FDLB_OK;
 }
 
@@ -369,9 +383,9 @@ static int set_state_dev(fdlb_ctx *h, int ci, const double *fields, const double
   int *tmp = h->d_map + 4 * (h->map_cap - (mt.size() + mu.size()) / 4);
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, c.qh > MAXQH, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, c.qh > MAXQH, CTILE, h->stream));
   HIPCHK(launch_fill(P, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, noise ? 1 : 0, h->stream));
-  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, c.qh > MAXQH, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, c.qh > MAXQH, CTILE, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   c.steps = 0;
   c.last_resid = INFINITY;
@@ -503,7 +517,7 @@ extern "C" int fdlb_moments(fdlb_handle h, int c, double *out) {
   int *tmp = h->d_map + 4 * (h->map_cap - mt.size() / 4);
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(launch_table(ch.prec, h->d_cases, tmp, (int)(mt.size() / 4), TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH,
-                      h->stream));
+                      CTILE, h->stream));
   HIPCHK(hipMemcpyAsync(out, h->hdev[c].mom, sizeof(double) * FDLB_NMOM * ch.nx, hipMemcpyDeviceToHost, h->stream));
   if (!was) { h->hdev[c].active = 0; r = upload_cases(h); if (r) return r; }
   HIPCHK(hipStreamSynchronize(h->stream));
@@ -636,7 +650,7 @@ static int refresh_partials(fdlb_ctx *h, int c) {
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(launch_partials(ch.prec, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, h->stream));
-  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH, h->stream));
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH, CTILE, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return FDLB_OK;
 }
@@ -880,8 +894,8 @@ extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
         const int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
         hipEvent_t *e = ev[stage - 1][G];
         if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], h->stream));
-        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wide, h->stream, e[0],
-                            e[1]));
+        HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wideT[G], h->tileT[G],
+                            h->stream, e[0], e[1]));
         HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream,
                              e[2], e[3]));
       }

@@ -23,6 +23,11 @@ constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
 #define FDLB_CTILE 16
 #endif
 constexpr int CTILE = FDLB_CTILE;  // cells per table block
+// Table maps that would have at most SMALL_TABLE_MAP blocks of CTILE cells use
+// blocks of CTILE_SMALL cells instead: twice the blocks, each with half the
+// work, for small cases whose table pass is latency-bound.
+constexpr int CTILE_SMALL = 8;
+constexpr int SMALL_TABLE_MAP = 32;
 constexpr int CHALO = 6;       // moment halo of a table block
 #ifndef FDLB_TABLE_WIDE_MAX
 #define FDLB_TABLE_WIDE_MAX 128

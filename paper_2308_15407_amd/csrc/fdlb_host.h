@@ -50,9 +50,10 @@ enum {
 // (rmax: the largest 4 qh of the cases on the map)
 hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, long nsteps, hipStream_t s);
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
-// wide: the map may hold cases with qx_half > MAXQH (adds the wide pass)
+// wide: the map may hold cases with qx_half > MAXQH (adds the wide pass);
+// tile: the cells per block the map was built with (CTILE or CTILE_SMALL)
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
-                        bool wide, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
+                        bool wide, int tile, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // averaged density of the revised Enskog contact value (chi_mode 1 cases):
 // one block per NBAR_TILE cells; lds = bytes of the largest window of a tile
 constexpr int NBAR_TILE = 16;

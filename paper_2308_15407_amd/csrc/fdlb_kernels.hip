@@ -1,7 +1,7 @@
 // fdlb_kernels.hip -- gfx950 kernels of one FDLB stage (Sec. III.B).
 //
 // A stage is two launches over a flat block map that may span many cases:
-//   k_table  : per cell (16-cell tiles): moments of the stage input from the
+//   k_table  : per cell (16-cell tiles; 8 on small maps): moments of the stage input from the
 //              partial raw sums, closure (eq:chi, eq:viscosity, eq:tau,
 //              eq:prandtl), 6th-order gradients (Sec. III.B.3), the
 //              Shakhov/J1 polynomial (eq:j0, eq:j1) and its per-axis lattice
@@ -300,7 +300,7 @@ __global__ void __launch_bounds__(512) k_nbar(const CaseDev *__restrict__ cases,
 // MAXQH_WIDE) with an NB_WIDE-node base rule and the rows read from global
 // memory.  Both run on the same launch map; each skips the other's cases, and
 // the wall blocks of every case belong to the standard instantiation.
-template <typename T, int NT, bool WIDE>
+template <typename T, int NT, bool WIDE, int TS>
 __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases, const int4 *__restrict__ map,
                                                int mode, int gin) {
   // launch maps list only active cases; padding entries have bm.x < 0
@@ -313,16 +313,16 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   }
   if ((c.qh > MAXQH) != WIDE) return;
   constexpr int NBX = WIDE ? NB_WIDE : NB;   // base rule nodes
-  constexpr int W = CTILE + 2 * CHALO;
+  constexpr int W = TS + 2 * CHALO;
   __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy
   __shared__ double s_l[3][W];      // ln n, ln chi, ln T
   __shared__ double s_chi[W];       // contact value chi
-  __shared__ double s_c[CTILE][20]; // n, ux, uy, T, invtau, C[13]
+  __shared__ double s_c[TS][20]; // n, ux, uy, T, invtau, C[13]
   // the raw sums of the tile and its halo first, then the base weights G
   // (rows padded by one double so that lanes reading different cells or
   // nodes fall in different banks)
   static_assert(NRAW * W <= 256, "one thread per raw moment and cell of the tile and halo");
-  constexpr int SCR = NRAW * W > CTILE * 2 * (NBX + 1) ? NRAW * W : CTILE * 2 * (NBX + 1);
+  constexpr int SCR = NRAW * W > TS * 2 * (NBX + 1) ? NRAW * W : TS * 2 * (NBX + 1);
   __shared__ double s_scr[SCR];
   double (*s_G)[2][NBX + 1] = reinterpret_cast<double (*)[2][NBX + 1]>(s_scr);
   __shared__ double s_red[NT];
@@ -333,8 +333,8 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   constexpr int NCST = WIDE ? 3 * MAXQH_WIDE + 3 * NBX + 2 * MAXQY * MAXQY
                             : 2 * MAXQH + 3 * NB + MAXQH * (NB + 1) + MAXQH + 2 * MAXQY * MAXQY;
   __shared__ double s_cst[NCST];
-  const int nx = c.nx, c0 = bm.y * CTILE;
-  const int own = min(CTILE, nx - c0);
+  const int nx = c.nx, c0 = bm.y * TS;
+  const int own = min(TS, nx - c0);
   const int tid = threadIdx.x;
   const double *lat = c.lat;
   const LatOff lo = c.lo;
@@ -556,7 +556,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
     for (int q = 0; q < 13; q++) s_c[tid][5 + q] = C[q];
   } else if (tid >= 64) {
     // ---- half-range base weights per owned cell and half (waves 1..3) ----
-    static_assert(CTILE <= 64, "the closure runs on the first wave");
+    static_assert(TS <= 64, "the closure runs on the first wave");
     for (int it = tid - 64; it < own * 2 * NBX; it += NT - 64) {
       const int cl = it / (2 * NBX), h = (it / NBX) & 1, m = it % NBX;
       const double ux = s_m[1][cl + CHALO], T_ = s_m[3][cl + CHALO];
@@ -1169,24 +1169,32 @@ hipError_t launch_nbar(int prec, const CaseDev *cases, const int *map, int nbloc
 }
 
 hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblocks, int mode, int gin,
-                        bool wide, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+                        bool wide, int tile, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (nblocks <= 0) return hipSuccess;
   const int4 *m = (const int4 *)map;
+  if (tile == CTILE_SMALL) {
+    // small maps (built with CTILE_SMALL cells per block; never with wide cases)
+    if (wide || nblocks > TABLE_WIDE_MAX) return hipErrorInvalidValue;
+    if (prec == 0) launch_k(k_table<double, 512, false, CTILE_SMALL>, dim3(nblocks), dim3(512), 0, s, e0, e1, cases, m, mode, gin);
+    else launch_k(k_table<float, 512, false, CTILE_SMALL>, dim3(nblocks), dim3(512), 0, s, e0, e1, cases, m, mode, gin);
+    return hipGetLastError();
+  }
+  if (tile != CTILE) return hipErrorInvalidValue;
   // small maps are latency-bound: twice the threads per block shorten the
   // per-phase work of each thread; large maps keep more blocks resident
   hipEvent_t e1s = wide ? nullptr : e1;
   if (nblocks <= TABLE_WIDE_MAX) {
-    if (prec == 0) launch_k(k_table<double, 512, false>, dim3(nblocks), dim3(512), 0, s, e0, e1s, cases, m, mode, gin);
-    else launch_k(k_table<float, 512, false>, dim3(nblocks), dim3(512), 0, s, e0, e1s, cases, m, mode, gin);
+    if (prec == 0) launch_k(k_table<double, 512, false, CTILE>, dim3(nblocks), dim3(512), 0, s, e0, e1s, cases, m, mode, gin);
+    else launch_k(k_table<float, 512, false, CTILE>, dim3(nblocks), dim3(512), 0, s, e0, e1s, cases, m, mode, gin);
   } else {
-    if (prec == 0) launch_k(k_table<double, 256, false>, dim3(nblocks), dim3(256), 0, s, e0, e1s, cases, m, mode, gin);
-    else launch_k(k_table<float, 256, false>, dim3(nblocks), dim3(256), 0, s, e0, e1s, cases, m, mode, gin);
+    if (prec == 0) launch_k(k_table<double, 256, false, CTILE>, dim3(nblocks), dim3(256), 0, s, e0, e1s, cases, m, mode, gin);
+    else launch_k(k_table<float, 256, false, CTILE>, dim3(nblocks), dim3(256), 0, s, e0, e1s, cases, m, mode, gin);
   }
   // orders above MAXQH: a second pass over the same map (after the first, so
   // the wall fluxes are in place)
   if (wide) {
-    if (prec == 0) hipLaunchKernelGGL((k_table<double, 512, true>), dim3(nblocks), dim3(512), 0, s, cases, m, mode, gin);
-    else hipLaunchKernelGGL((k_table<float, 512, true>), dim3(nblocks), dim3(512), 0, s, cases, m, mode, gin);
+    if (prec == 0) hipLaunchKernelGGL((k_table<double, 512, true, CTILE>), dim3(nblocks), dim3(512), 0, s, cases, m, mode, gin);
+    else hipLaunchKernelGGL((k_table<float, 512, true, CTILE>), dim3(nblocks), dim3(512), 0, s, cases, m, mode, gin);
     if (e1) { hipError_t r = hipEventRecord(e1, s); if (r != hipSuccess) return r; }
   }
   return hipGetLastError();
