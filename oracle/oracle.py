@@ -91,6 +91,8 @@ def lib():
         L.orc_set_weno_ideal.argtypes = [P, I]
         L.orc_set_weno_ideal.restype = None
         L.orc_create_reduced1d.argtypes = [C.POINTER(OrcParams)]
+        L.orc_create_reduced2d.restype = P
+        L.orc_create_reduced2d.argtypes = [C.POINTER(OrcParams)]
         _lib = L
     return _lib
 
@@ -104,9 +106,11 @@ DEFAULTS = dict(flow=0, kn=0.1, eta0=0.05, t_left=1.0, t_right=1.0, uy_left=0.0,
 class Oracle:
     """One FDLB case on the CPU in FP64 (see fdlb_oracle.c).  reduced1d=True
     builds the paper's reduced 1D model of the Fourier flow instead: phi and
-    theta on the 2 qx_half x-nodes (rows 0..2Q-1 and 2Q..4Q-1 of get_f)."""
+    theta on the 2 qx_half x-nodes (rows 0..2Q-1 and 2Q..4Q-1 of get_f);
+    reduced2d=True the reduced 2D model: phi and theta on the 2 qx_half x qy
+    (x, y) nodes (rows kx*qy + ky, then the theta rows)."""
 
-    def __init__(self, reduced1d=False, **kw):
+    def __init__(self, reduced1d=False, reduced2d=False, **kw):
         d = dict(DEFAULTS)
         unknown = set(kw) - set(d)
         if unknown:
@@ -114,8 +118,10 @@ class Oracle:
         d.update(kw)
         self.params = d
         self._p = OrcParams(**d)
-        self.reduced1d = bool(reduced1d)
-        self._h = (lib().orc_create_reduced1d if reduced1d else lib().orc_create)(C.byref(self._p))
+        self.reduced1d, self.reduced2d = bool(reduced1d), bool(reduced2d)
+        create = lib().orc_create_reduced2d if reduced2d else (lib().orc_create_reduced1d if reduced1d
+                                                                 else lib().orc_create)
+        self._h = create(C.byref(self._p))
         if not self._h:
             raise ValueError("oracle rejected parameters %r" % d)
         self.nx = d["nx"]

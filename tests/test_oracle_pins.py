@@ -555,3 +555,38 @@ def test_reduced_1d_model_conserves_mass_and_keeps_the_wall_equilibrium():
     assert np.max(np.abs(o.get_f() - f0)) < 1e-12 * np.max(np.abs(f0))
     with pytest.raises(ValueError):
         O.Oracle(reduced1d=True, **dict(cfg, uy_left=0.1))
+
+
+@pytest.mark.parametrize("flow,extra", [("couette", dict(flow=I.COUETTE, uy_left=-0.3, uy_right=0.3)),
+                                        ("poiseuille", dict(flow=I.POISEUILLE, ay=0.05))])
+@pytest.mark.parametrize("collision,shear", [(I.SHAKHOV_DENSE, 1), (I.BGK, 0), (I.SHAKHOV_FIXED, 1)])
+def test_reduced_2d_model_is_the_z_sum_of_the_3d_lattice(flow, extra, collision, shear):
+    """The paper's reduced 2D equations (eq:evolution_2D with eq:f2D_expanded
+    and eq:j1_expanded_2D, J1^theta with the prefactor k_B T of theta^S, and
+    with j1_shear = 1 the 3D operator's xi_x xi_y du_y/dx term) against the 3D
+    lattice with Q_z = 4: phi = sum over p_z of f, theta = the sum weighted by
+    p_z^2.  With the ideal WENO weights every step commutes with these sums,
+    body force included, so the two agree to rounding over many steps."""
+    qh, qy, nx = 5, 4, 24
+    cfg = dict(I.BASE, nx=nx, qx_half=qh, qy=qy, qz=4, kn=0.08, eta0=0.15, collision=collision, pr_fixed=0.6,
+               j1_shear=shear, t_left=0.9, t_right=1.2, t_init=1.0, **extra)
+    o3 = O.Oracle(**cfg)
+    o2 = O.Oracle(reduced2d=True, **cfg)
+    f = I.smooth_fields(11, nx, amp=0.08)
+    o3.set_state(f)
+    o2.set_state(f)
+    o3.set_weno_ideal()
+    o2.set_weno_ideal()
+    px, py, pz, w = o3.lattice()
+    pz2 = (pz ** 2).reshape(2 * qh * qy, 4)[0]
+    for st in (0, 20):
+        o3.step(st)
+        o2.step(st)
+        F = o3.get_f().reshape(2 * qh * qy, 4, nx)
+        phi, theta = F.sum(axis=1), np.einsum('kjx,j->kx', F, pz2)
+        g = o2.get_f().reshape(2, 2 * qh * qy, nx)
+        assert np.max(np.abs(phi - g[0])) < 1e-13 * np.max(np.abs(g[0])), st
+        assert np.max(np.abs(theta - g[1])) < 1e-13 * np.max(np.abs(g[1])), st
+        m3, m2 = o3.moments(), o2.moments()
+        for q in range(10):
+            assert np.max(np.abs(m3[q] - m2[q])) < 1e-13, (st, q)
