@@ -222,19 +222,24 @@ const char *fdlb_mlp_last_error(void);
 /* Release host-side state (the caller still owns the workspace). */
 void fdlb_destroy(fdlb_handle h);
 
-/* ---- reduced 1D model of the Fourier flow (Sec. II.B, 1D flows) ----------
-   The paper's own formulation of 1D flows: the reduced distributions
-   phi = int f dp_y dp_z and theta = int (p_y^2 + p_z^2) f dp_y dp_z on the
-   2 qx_half half-range x-nodes (eq:evolution_1D with phi^S, theta^S, J1^phi,
-   J1^theta; moments eq:macro1D).  A case is an fdlb_params whose walls and
-   initial state have u_y = 0, a_y = 0, chi_mode 0, precision FDLB_F64 and
-   qx_half <= 32 (qy, qz are ignored).  State layout: [4 qx_half][nx] doubles,
-   rows [0, 2 qx_half) phi and [2 qx_half, 4 qx_half) theta, nodes in the
-   order of fdlb_case_lattice's x-nodes, cells contiguous.  Each TVD-RK3 step
-   is three launches of one fused kernel; the calls follow the 3D solver's
+/* ---- reduced models (Sec. II.B) ------------------------------------------
+   The paper's own formulation of the channel flows, chosen by the flow field:
+   - Fourier (flow 0), 1D: phi = int f dp_y dp_z and theta = int (p_y^2 +
+     p_z^2) f dp_y dp_z on the 2 qx_half half-range x-nodes (eq:evolution_1D,
+     moments eq:macro1D).  Walls and initial state at u_y = 0, a_y = 0; qy is
+     ignored.  Rows: [0, 2 qx_half) phi, then theta.
+   - Couette and Poiseuille (flows 1, 2), 2D: phi = int f dp_z and theta =
+     int p_z^2 f dp_z on the 2 qx_half x qy (x, y) nodes (eq:evolution_2D with
+     the body force, moments eq:macro2D), 4 qx_half qy <= 256.  Rows: phi
+     (kx, ky) at kx qy + ky, then theta in the same order.
+   Every case: chi_mode 0, precision FDLB_F64, qx_half <= 32; qz is ignored;
+   one dimension per batch.  State layout: [rows][nx] doubles, x-nodes in
+   the order of fdlb_case_lattice's, cells contiguous.  Each TVD-RK3 step is
+   three launches of one fused kernel; the calls follow the 3D solver's
    conventions (caller-owned workspace, stream, error codes). */
 typedef struct fdlb_r1_ctx *fdlb_r1_handle;
-/* Device workspace bytes for ncases reduced cases (0 when a case is invalid). */
+/* Device workspace bytes for ncases reduced cases (0 when a case is invalid
+   or the batch mixes dimensions). */
 size_t fdlb_r1_workspace_bytes(const fdlb_params *cases, int ncases);
 /* Set up the cases in dev_workspace on hip_stream, each at its uniform
    initial state (n_init, T_init at rest). */
@@ -242,14 +247,15 @@ int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_workspace, size
                  void *hip_stream, fdlb_r1_handle *out);
 /* Advance every case by nsteps steps (asynchronous). */
 int fdlb_r1_step(fdlb_r1_handle h, long nsteps);
-/* Moments of case c into host_out[FDLB_NMOM][nx] (u_y, q_y, P_xy are 0;
-   P_yy = P_zz = half the theta sum) (synchronises). */
+/* Moments of case c into host_out[FDLB_NMOM][nx] (1D: u_y, q_y, P_xy are 0
+   and P_yy = P_zz = half the theta sum; 2D: P_zz is the theta sum)
+   (synchronises). */
 int fdlb_r1_moments(fdlb_r1_handle h, int c, double *host_out);
 /* Replace the state of case c by the reduced Grad-13-type state of host
-   fields[6][nx] (n, u_x, u_y, T, q_x, P_xy; u_y and P_xy are ignored),
-   optionally times (1 + noise[4 qx_half][nx]) (synchronises). */
+   fields[6][nx] (n, u_x, u_y, T, q_x, P_xy; 1D ignores u_y and P_xy),
+   optionally times (1 + noise[rows][nx]) (synchronises). */
 int fdlb_r1_set_state(fdlb_r1_handle h, int c, const double *fields, const double *noise);
-/* Copy phi and theta of case c to host_f[4 qx_half][nx] (synchronises). */
+/* Copy phi and theta of case c to host_f[rows][nx] (synchronises). */
 int fdlb_r1_get_f(fdlb_r1_handle h, int c, double *host_f);
 /* Time step of case c. */
 int fdlb_r1_dt(fdlb_r1_handle h, int c, double *dt);

@@ -97,14 +97,18 @@ struct CaseDev {
   double *noise;        // staging [K][nx] for set_state (may be unused)
 };
 
-// One case of the reduced 1D model (Sec. II.B, 1D flows): phi and theta on
-// the 2 qh x-nodes, rows [0, 2qh) and [2qh, 4qh) of [R][nx] arrays (R = 4 qh).
-constexpr int R1_TILE = 32;    // cells per block of the reduced stage kernel
+// One case of a reduced model (Sec. II.B): phi and theta on the 2 qh x-nodes
+// (1D flows, qy = 1) or the 2 qh x qy (x, y) nodes (2D flows).  Rows of the
+// [R][nx] arrays: phi (kx, ky) at kx qy + ky, then theta; R = 4 qh qy.
+constexpr int R1_TILE = 32;    // cells per block of the reduced stage kernel (up to 128 rows)
+constexpr int R1_TILE_2 = 16;  // cells per block for 129..256 rows
+constexpr int R1_RMAX = 256;   // rows of a reduced case
 constexpr int R1_HALO = 6;     // moment halo (the one-sided wall stencils reach 6 cells)
 struct R1Dev {
-  int nx, qh, R;
-  int collision;
-  double pr_fixed, eta0, tau_pre, dt;
+  int nx, qh, qy, R;
+  int dim;              // 1 or 2
+  int collision, j1_shear;
+  double pr_fixed, eta0, tau_pre, dt, ay;
   const double *lat;    // lattice constants of the case (px, base rule, lambda, c_k, FD weights)
   LatOff lo;
   const double *invdx;  // [nx] 1 / (cell width)

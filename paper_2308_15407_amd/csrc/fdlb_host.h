@@ -45,10 +45,13 @@ enum {
 
 // kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
-// reduced 1D model: nsteps TVD-RK3 steps of every case (map: int2 {case, tile}
-// per block of R1_TILE cells), and the moments of case c into its mom array
-// (rmax: the largest 4 qh of the cases on the map)
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, long nsteps, hipStream_t s);
+// reduced models: nsteps TVD-RK3 steps of every case (map: int2 {case, tile}
+// per block of r1_tile(rmax) cells; rmax: the largest row count of the cases;
+// dim: 1 or 2, the same for every case), and the moments of case c into its
+// mom array
+int r1_tile(int rmax);
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, long nsteps,
+                          hipStream_t s);
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
 // wide: the map may hold cases with qx_half > MAXQH (adds the wide pass);
 // tile: the cells per block the map was built with (CTILE or CTILE_SMALL)

@@ -1283,41 +1283,43 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 
 
 // ---------------------------------------------------------------------------
-// reduced 1D model (Sec. II.B, 1D flows): one fused kernel per RK stage
+// reduced models (Sec. II.B): one fused kernel per RK stage
 // ---------------------------------------------------------------------------
-// A block owns R1_TILE cells of one case.  It stages phi and theta of its
-// cells and a halo of R1_HALO cells per side in LDS, and then, without going
-// back to memory: the moments (eq:macro1D) of every staged cell, the wall
-// densities (tiles at a wall), the closure and the targets of its cells
-// (phi^S + tau J1^phi and theta^S + tau J1^theta as polynomials in xi times
-// f_x^MB, each projected on the half-range lattice), and the update of all
-// 4 qh rows of its cells: WENO-5 advection with the diffuse-wall rules of the
-// 3D pass, relaxation and the TVD-RK3 combination (eq:rk3).  The rows are
-// few (4 qh <= 128), so the whole stage fits one pass over the data.  RM is
-// the largest row count of the launch (64: qh <= 16, else 128), which sizes
-// the LDS and so the blocks resident per CU.
-template <int STAGE, int RM>
+// A block owns TS cells of one case.  It stages phi and theta of its cells and
+// a halo of R1_HALO cells per side in LDS, and then, without going back to
+// memory: the moments (eq:macro1D, eq:macro2D) of every staged cell, the wall
+// densities (tiles whose stencils reach a wall), the closure and the targets
+// of its cells (phi^S + tau J1^phi and theta^S + tau J1^theta as polynomials
+// in xi times the Maxwellian, projected per axis), and the update of every
+// row of its cells: WENO-5 advection with the diffuse-wall rules of the 3D
+// pass, the body force on the y-nodes (2D), relaxation and the TVD-RK3
+// combination (eq:rk3).  D is the dimension of the reduced model, RM the
+// largest row count of the launch (it sizes the LDS; TS = 32 cells up to 128
+// rows, 16 above).
+template <int STAGE, int RM, int D>
 __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
+  constexpr int TS = RM <= 128 ? R1_TILE : R1_TILE_2;
+  constexpr int W = TS + 2 * R1_HALO, QYM = D == 2 ? MAXQY : 1;
   const int2 bm = map[blockIdx.x];
   const R1Dev &c = cases[bm.x];
-  constexpr int W = R1_TILE + 2 * R1_HALO;
   __shared__ double s_g[RM][W];
-  __shared__ double s_t[RM][R1_TILE];
-  __shared__ double s_G[R1_TILE][2][NB + 1];
-  __shared__ double s_m[4][W];    // n, u_x, T, q_x
-  __shared__ double s_l[3][W];    // ln n, ln chi, ln T
-  __shared__ double s_c[R1_TILE][12];
+  __shared__ double s_t[RM][TS];
+  __shared__ double s_G[TS][2][NB + 1];
+  __shared__ double s_m[6][W];              // n, u_x, u_y, T, q_x, q_y
+  __shared__ double s_l[3][W];              // ln n, ln chi, ln T
+  __shared__ double s_c[TS][2];             // n, 1/tau
+  __shared__ double s_y[TS][2][4][QYM];     // per y-node: sum_b P_ab Y_b (phi, theta)
   __shared__ double s_nw[2];
-  __shared__ double s_lam[RM / 4][NB + 1];  // Lagrange rows (padded by one: bank spread)
+  __shared__ double s_lam[D == 2 ? MAXQH : RM / 4][NB + 1];   // Lagrange rows (padded: bank spread)
   __shared__ double s_bh[2][NB];            // base nodes P_m and h_Q(P_m)
-  const int nx = c.nx, qh = c.qh, Q2 = 2 * qh, R = c.R;
-  const int c0 = bm.y * R1_TILE, own = min(R1_TILE, nx - c0);
+  const int nx = c.nx, qh = c.qh, qy = c.qy, Q2 = 2 * qh, Kh = Q2 * qy, R = c.R;
+  const int c0 = bm.y * TS, own = min(TS, nx - c0);
   const int tid = threadIdx.x;
   const double *lat = c.lat;
   const LatOff lo = c.lo;
   const double *gin = STAGE == 1 ? c.f : (STAGE == 2 ? c.g1 : c.g2);
   double *gout = STAGE == 1 ? c.g1 : (STAGE == 2 ? c.g2 : c.f);
-  constexpr int SW = 4, NS = R1_TILE / SW;   // update strips: 4 cells of one row
+  constexpr int SW = 4, NS = TS / SW;   // update strips: 4 cells of one row
 
   for (int it = tid; it < R * W; it += blockDim.x) {
     const int r = it / W, w = it - r * W, cell = c0 - R1_HALO + w;
@@ -1328,31 +1330,41 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   __syncthreads();
 
   // moments of the staged cells (8 lanes per cell, each summing every 8th
-  // node, then a butterfly over the 8 lanes); wall densities in the wall tiles
+  // phi row, then a butterfly over the 8 lanes); wall densities in the tiles
+  // whose stencils reach a wall
   static_assert(8 * W <= 448, "moment lanes stay below the wall threads");
   if (tid < 8 * W) {
     const int wc = tid >> 3, sub = tid & 7, cell = c0 - R1_HALO + wc;
     const bool live = cell >= 0 && cell < nx;   // uniform over the 8 lanes of a cell
-    double n = 0.0, jx = 0.0;
+    double n = 0.0, jx = 0.0, jy = 0.0;
     if (live)
-      for (int k = sub; k < Q2; k += 8) { n += s_g[k][wc]; jx += lat[lo.px + k] * s_g[k][wc]; }
-#pragma unroll
-    for (int off = 1; off < 8; off <<= 1) { n += __shfl_xor(n, off, 64); jx += __shfl_xor(jx, off, 64); }
-    const double ux = live ? jx / n : 0.0;
-    double pxx = 0.0, th = 0.0, qx = 0.0;
-    if (live)
-      for (int k = sub; k < Q2; k += 8) {
-        const double cx = lat[lo.px + k] - ux, ph = s_g[k][wc], tt = s_g[Q2 + k][wc];
-        pxx += cx * cx * ph; th += tt;
-        qx += cx * (0.5 * cx * cx * ph + 0.5 * tt);
+      for (int r = sub; r < Kh; r += 8) {
+        const double v = s_g[r][wc];
+        n += v; jx += lat[lo.px + r / qy] * v;
+        if (D == 2) jy += lat[lo.py + r % qy] * v;
       }
 #pragma unroll
     for (int off = 1; off < 8; off <<= 1) {
-      pxx += __shfl_xor(pxx, off, 64); th += __shfl_xor(th, off, 64); qx += __shfl_xor(qx, off, 64);
+      n += __shfl_xor(n, off, 64); jx += __shfl_xor(jx, off, 64); jy += __shfl_xor(jy, off, 64);
+    }
+    const double ux = live ? jx / n : 0.0, uy = live ? jy / n : 0.0;
+    double pin = 0.0, th = 0.0, qx = 0.0, qy_ = 0.0;   // pin: sum of |xi_in-plane|^2 phi
+    if (live)
+      for (int r = sub; r < Kh; r += 8) {
+        const double cx = lat[lo.px + r / qy] - ux, cy = D == 2 ? lat[lo.py + r % qy] - uy : 0.0;
+        const double ph = s_g[r][wc], tt = s_g[Kh + r][wc], c2 = cx * cx + cy * cy;
+        pin += c2 * ph; th += tt;
+        qx += cx * (0.5 * c2 * ph + 0.5 * tt);
+        if (D == 2) qy_ += cy * (0.5 * c2 * ph + 0.5 * tt);
+      }
+#pragma unroll
+    for (int off = 1; off < 8; off <<= 1) {
+      pin += __shfl_xor(pin, off, 64); th += __shfl_xor(th, off, 64);
+      qx += __shfl_xor(qx, off, 64); qy_ += __shfl_xor(qy_, off, 64);
     }
     if (live && sub == 0) {
-      const double T_ = (pxx + th) / (3.0 * n);
-      s_m[0][wc] = n; s_m[1][wc] = ux; s_m[2][wc] = T_; s_m[3][wc] = qx;
+      const double T_ = (pin + th) / (3.0 * n);
+      s_m[0][wc] = n; s_m[1][wc] = ux; s_m[2][wc] = uy; s_m[3][wc] = T_; s_m[4][wc] = qx; s_m[5][wc] = qy_;
       s_l[0][wc] = log(n); s_l[1][wc] = log(chi_cs(c.eta0 * n)); s_l[2][wc] = log(T_);
     }
   } else if (tid == 448 || tid == 480) {
@@ -1364,12 +1376,12 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     const bool here = wall == 0 ? c0 < 3 : c0 + own + 2 >= nx;
     if (here) {
       double in = 0.0;
-      for (int k = 0; k < Q2; k++) {
-        const double p = lat[lo.px + k];
+      const int w0 = wall == 0 ? R1_HALO : nx - 1 - c0 + R1_HALO;   // the wall cell
+      const int st = wall == 0 ? 1 : -1;                             // into the domain
+      for (int r = 0; r < Kh; r++) {
+        const double p = lat[lo.px + r / qy];
         if ((wall == 0) != (p < 0.0)) continue;
-        const int w0 = wall == 0 ? R1_HALO : nx - 1 - c0 + R1_HALO;   // the wall cell
-        const int st = wall == 0 ? 1 : -1;                             // into the domain
-        const double v0 = s_g[k][w0 + 2 * st], v1 = s_g[k][w0 + st], v2 = s_g[k][w0];
+        const double v0 = s_g[r][w0 + 2 * st], v1 = s_g[r][w0 + st], v2 = s_g[r][w0];
         in += p * (v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0));
       }
       s_nw[wall] = -in / c.wallD[wall];
@@ -1377,14 +1389,16 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   }
   __syncthreads();
 
-  // closure and the coefficients of the two target polynomials per owned cell
+  // closure and the target polynomials per owned cell, folded with the y
+  // projections into the per-node factors s_y
   if (tid < own) {
     const int i = c0 + tid, li = tid + R1_HALO;
-    double g[4];
+    double g[5];
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-      const double *src = q < 3 ? s_l[q] : s_m[1];
+    for (int q = 0; q < 5; q++) {
+      const double *src = q < 3 ? s_l[q] : (q == 3 ? s_m[1] : s_m[2]);
       double d = 0.0;
+      if (q == 4 && D == 1) { g[q] = 0.0; continue; }
       if (i >= 3 && i <= nx - 4) {
         d = (src[li + 1] - src[li - 1]) * 0.75 - (src[li + 2] - src[li - 2]) * 0.15 +
             (src[li + 3] - src[li - 3]) * (1.0 / 60.0);
@@ -1396,7 +1410,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       }
       g[q] = d * c.invdx[i];
     }
-    const double n = s_m[0][li], ux = s_m[1][li], T_ = s_m[2][li], qx = s_m[3][li];
+    const double n = s_m[0][li], uy = s_m[2][li], T_ = s_m[3][li], qx = s_m[4][li], qy_ = s_m[5][li];
     const double eta = c.eta0 * n, chi = chi_cs(eta), brc = 4.0 * eta * chi;
     double tau = 0.0, itau = 0.0;
     if (c.tau_pre > 0.0) {
@@ -1409,39 +1423,74 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     else if (c.collision == 2)
       Pr = 2.0 / 3.0 * (1.0 + 0.8 * brc + 4.0 / 25.0 * (1.0 + 12.0 / M_PI) * brc * brc) /
            (1.0 + 1.2 * brc + 9.0 / 25.0 * (1.0 + 32.0 / (9.0 * M_PI)) * brc * brc);
-    // phi: 1 + s0 (xi^2/T - 3) xi q_x + tau J1^phi / f^MB; theta / (2T):
-    // 1 + s0 (xi^2/T - 1) xi q_x + tau J1^theta / (2T f^MB), s0 = (1-Pr)/(5 n T^2)
     const double s0 = (1.0 - Pr) / (5.0 * n * T_ * T_), iT = 1.0 / T_;
-    double cp[4] = {1.0, -3.0 * s0 * qx, 0.0, s0 * qx * iT};
-    double ct[4] = {1.0, -s0 * qx, 0.0, s0 * qx * iT};
-    if (itau > 0.0 && brc > 0.0) {
-      const double A = -tau * brc, g1 = g[1] + 2.0 * g[0];   // dln chi + 2 dln rho
-      cp[0] -= A * 0.6 * g[3]; cp[1] += A * (g1 + 0.1 * g[2]); cp[2] += A * 0.6 * g[3] * iT; cp[3] += A * 0.3 * g[2] * iT;
-      ct[0] -= A * 0.2 * g[3]; ct[1] += A * (g1 + 0.7 * g[2]); ct[2] += A * 0.6 * g[3] * iT; ct[3] += A * 0.3 * g[2] * iT;
-    }
-    s_c[tid][0] = n; s_c[tid][1] = ux; s_c[tid][2] = T_; s_c[tid][3] = itau;
+    const bool j1 = itau > 0.0 && brc > 0.0;
+    const double A = j1 ? -tau * brc : 0.0, g1 = g[1] + 2.0 * g[0];   // dln chi + 2 dln rho
+    if (D == 1) {
+      // phi: 1 + s0 (xi^2/T - 3) xi q_x + tau J1^phi / f^MB; theta / (2T):
+      // 1 + s0 (xi^2/T - 1) xi q_x + tau J1^theta / (2T f^MB)
+      const double cp[4] = {1.0 - A * 0.6 * g[3], -3.0 * s0 * qx + A * (g1 + 0.1 * g[2]), A * 0.6 * g[3] * iT,
+                            s0 * qx * iT + A * 0.3 * g[2] * iT};
+      const double ct[4] = {1.0 - A * 0.2 * g[3], -s0 * qx + A * (g1 + 0.7 * g[2]), A * 0.6 * g[3] * iT,
+                            s0 * qx * iT + A * 0.3 * g[2] * iT};
 #pragma unroll
-    for (int a = 0; a < 4; a++) { s_c[tid][4 + a] = cp[a]; s_c[tid][8 + a] = 2.0 * T_ * ct[a]; }
+      for (int a = 0; a < 4; a++) { s_y[tid][0][a][0] = cp[a]; s_y[tid][1][a][0] = 2.0 * T_ * ct[a]; }
+    } else {
+      // P[w][a][b]: coefficient of xi_x^a xi_y^b in phi^S_2D + tau J1^phi_2D
+      // (w = 0) and in (theta^S_2D + tau J1^theta_2D) / T (w = 1), with the
+      // 3D operator's (2/5)(xi_x xi_y / T) du_y/dx term when j1_shear = 1
+      double P[2][4][4];
+#pragma unroll
+      for (int w = 0; w < 2; w++) {
+#pragma unroll
+        for (int a = 0; a < 4; a++)
+#pragma unroll
+          for (int b = 0; b < 4; b++) P[w][a][b] = 0.0;
+        const double cq = w == 0 ? 4.0 : 2.0, cu = w == 0 ? 2.0 : 1.0, cT = w == 0 ? -2.0 / 3.0 : 4.0 / 3.0;
+        P[w][0][0] = 1.0 - A * 0.4 * cu * g[3];
+        P[w][3][0] = s0 * qx * iT + A * 0.3 * iT * g[2];
+        P[w][1][2] = s0 * qx * iT + A * 0.3 * iT * g[2];
+        P[w][1][0] = -cq * s0 * qx + A * (g1 + 0.3 * cT * g[2]);
+        P[w][2][1] = s0 * qy_ * iT;
+        P[w][0][3] = s0 * qy_ * iT;
+        P[w][0][1] = -cq * s0 * qy_;
+        P[w][2][0] = A * 0.6 * iT * g[3];
+        P[w][0][2] = A * 0.2 * iT * g[3];
+        P[w][1][1] = c.j1_shear ? A * 0.4 * iT * g[4] : 0.0;
+      }
+      for (int ky = 0; ky < qy; ky++) {
+        double Y[4];
+        full_axis_values(uy, T_, qy, lat + lo.Hy + ky * qy, Y);
+#pragma unroll
+        for (int w = 0; w < 2; w++)
+#pragma unroll
+          for (int a = 0; a < 4; a++)
+            s_y[tid][w][a][ky] = (w == 0 ? 1.0 : T_) *
+                                 (P[w][a][0] * Y[0] + P[w][a][1] * Y[1] + P[w][a][2] * Y[2] + P[w][a][3] * Y[3]);
+      }
+    }
+    s_c[tid][0] = n; s_c[tid][1] = itau;
   } else if (tid >= 64) {
     // half-range base weights per owned cell and half
     for (int it = tid - 64; it < own * 2 * NB; it += blockDim.x - 64) {
       const int cl = it / (2 * NB), h = (it / NB) & 1, m = it % NB;
       const int w = cl + R1_HALO;
-      const double u = h == 0 ? s_m[1][w] : -s_m[1][w], T_ = s_m[2][w];
+      const double u = h == 0 ? s_m[1][w] : -s_m[1][w], T_ = s_m[3][w];
       const double d = s_bh[0][m] - u;
       s_G[cl][h][m] = exp(lat[lo.bA + m] - d * d / (2.0 * T_)) * rsqrt(T_);
     }
   }
   __syncthreads();
 
-  // targets: X_a[k] = Proj[g (p - u)^a] at node k (both halves), then
-  // phi_t = n sum_a cp_a X_a and theta_t = n sum_a (2T ct_a) X_a; an item is
-  // one cell and half and a pair of nodes, which share the base-weight reads
+  // targets: X_a[k] = Proj[g (p - u)^a] at x-node k (both halves), then per
+  // y-node phi_t = n sum_a X_a s_y[0][a] and theta_t = n sum_a X_a s_y[1][a];
+  // an item is one cell and half and a pair of x-nodes, which share the
+  // base-weight reads
   const int npair = (qh + 1) / 2;
   for (int it = tid; it < own * 2 * npair; it += blockDim.x) {
     const int cl = it % own, hk = it / own, h = hk / npair, k0 = 2 * (hk - h * npair);
     const int k1 = min(k0 + 1, qh - 1);
-    const double u = h == 0 ? s_c[cl][1] : -s_c[cl][1];
+    const double u = h == 0 ? s_m[1][cl + R1_HALO] : -s_m[1][cl + R1_HALO];
     const double *Gc = s_G[cl][h];
     const double *l0 = s_lam[k0], *l1 = s_lam[k1];
     double x0a = 0.0, x0b = 0.0, mb0 = 0.0, mb1 = 0.0, mb2 = 0.0;
@@ -1460,23 +1509,27 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       const double dk = lat[lo.px + k] - u, ck = lat[lo.ck + k];
       const double X[4] = {x0, sg * (dk * x0 + ck * mb0), dk * dk * x0 + ck * (dk * mb0 + mb1),
                            sg * (dk * dk * dk * x0 + ck * (dk * dk * mb0 + dk * mb1 + mb2))};
-      double tp = 0.0, tt = 0.0;
+      const int kx = h * qh + k;
+      for (int ky = 0; ky < qy; ky++) {
+        double tp = 0.0, tt = 0.0;
 #pragma unroll
-      for (int a = 0; a < 4; a++) { tp += s_c[cl][4 + a] * X[a]; tt += s_c[cl][8 + a] * X[a]; }
-      s_t[h * qh + k][cl] = n * tp;
-      s_t[Q2 + h * qh + k][cl] = n * tt;
+        for (int a = 0; a < 4; a++) { tp += s_y[cl][0][a][D == 2 ? ky : 0] * X[a]; tt += s_y[cl][1][a][D == 2 ? ky : 0] * X[a]; }
+        s_t[kx * qy + ky][cl] = n * tp;
+        s_t[Kh + kx * qy + ky][cl] = n * tt;
+      }
     }
   }
   __syncthreads();
 
-  // advection, relaxation and the RK combination: a thread takes one row and
-  // a strip of 4 owned cells, reconstructing the strip's 5 faces once
+  // advection, body force, relaxation and the RK combination: a thread takes
+  // one row and a strip of 4 owned cells, reconstructing the strip's 5 faces once
   const double nwl = c0 < 3 ? s_nw[0] : 0.0, nwr = c0 + own + 2 >= nx ? s_nw[1] : 0.0;
   for (int it = tid; it < R * NS; it += blockDim.x) {
     const int r = it / NS, q = it - r * NS, cl0 = q * SW;
     if (cl0 >= own) continue;
     const int ncl = min(SW, own - cl0);
-    const double p = lat[lo.px + (r % Q2)];
+    const int rh = r % Kh, ky = rh % qy;
+    const double p = lat[lo.px + rh / qy];
     const double *row = s_g[r];
     const double fwl = nwl * c.gw[r], fwr = nwr * c.gw[R + r];
     // face j (left face of cell j) in the upwind frame, with the wall rules:
@@ -1521,7 +1574,13 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       const int cl = cl0 + u, i = c0 + cl;
       const double fr = face(i + 1);
       const double cen = row[cl + R1_HALO];
-      const double L = (s_t[r][cl] - cen) * s_c[cl][3] - p * (fr - fl) * c.invdx[i];
+      double L = (s_t[r][cl] - cen) * s_c[cl][1] - p * (fr - fl) * c.invdx[i];
+      if (D == 2 && c.ay != 0.0) {
+        // -a_y d/dp_y on the y-nodes of this x-node and population (App. A kernel)
+        double sF = 0.0;
+        for (int k2 = 0; k2 < qy; k2++) sF += lat[lo.kmat + ky * qy + k2] * s_g[r - ky + k2][cl + R1_HALO];
+        L -= c.ay * sF;
+      }
       const double adv = cen + c.dt * L;
       double o;
       if (STAGE == 1) o = adv;
@@ -1535,44 +1594,62 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   }
 }
 
-// moments [FDLB_NMOM][nx] of the reduced state f^n: n, u_x, u_y = 0, T, q_x,
-// q_y = 0, P_xx, P_xy = 0, P_yy = P_zz = theta / 2 (y and z are equivalent)
+// moments [FDLB_NMOM][nx] of the reduced state f^n: n, u_x, u_y, T, q_x, q_y,
+// P_xx, P_xy, P_yy, P_zz (1D: u_y = q_y = P_xy = 0 and P_yy = P_zz = half the
+// theta sum; 2D: P_zz = the theta sum)
 __global__ void k_r1_moments(const R1Dev *__restrict__ cases, int c_idx) {
   const R1Dev &c = cases[c_idx];
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.nx) return;
-  const int nx = c.nx, Q2 = 2 * c.qh;
-  const double *px = c.lat + c.lo.px;
-  double n = 0.0, jx = 0.0;
-  for (int k = 0; k < Q2; k++) { n += c.f[(size_t)k * nx + i]; jx += px[k] * c.f[(size_t)k * nx + i]; }
-  const double ux = jx / n;
-  double pxx = 0.0, th = 0.0, qx = 0.0;
-  for (int k = 0; k < Q2; k++) {
-    const double cx = px[k] - ux, ph = c.f[(size_t)k * nx + i], tt = c.f[(size_t)(Q2 + k) * nx + i];
-    pxx += cx * cx * ph; th += tt;
-    qx += cx * (0.5 * cx * cx * ph + 0.5 * tt);
+  const int nx = c.nx, qy = c.qy, Kh = 2 * c.qh * qy;
+  const double *px = c.lat + c.lo.px, *py = c.lat + c.lo.py;
+  const bool two = c.dim == 2;
+  double n = 0.0, jx = 0.0, jy = 0.0;
+  for (int r = 0; r < Kh; r++) {
+    const double v = c.f[(size_t)r * nx + i];
+    n += v; jx += px[r / qy] * v;
+    if (two) jy += py[r % qy] * v;
+  }
+  const double ux = jx / n, uy = jy / n;
+  double pxx = 0.0, pxy = 0.0, pyy = 0.0, th = 0.0, qx = 0.0, qy_ = 0.0;
+  for (int r = 0; r < Kh; r++) {
+    const double cx = px[r / qy] - ux, cy = two ? py[r % qy] - uy : 0.0;
+    const double ph = c.f[(size_t)r * nx + i], tt = c.f[(size_t)(Kh + r) * nx + i], c2 = cx * cx + cy * cy;
+    pxx += cx * cx * ph; pxy += cx * cy * ph; pyy += cy * cy * ph; th += tt;
+    qx += cx * (0.5 * c2 * ph + 0.5 * tt); qy_ += cy * (0.5 * c2 * ph + 0.5 * tt);
   }
   double *mo = c.mom;
-  mo[i] = n; mo[nx + i] = ux; mo[2 * nx + i] = 0.0; mo[3 * nx + i] = (pxx + th) / (3.0 * n);
-  mo[4 * nx + i] = qx; mo[5 * nx + i] = 0.0; mo[6 * nx + i] = pxx; mo[7 * nx + i] = 0.0;
-  mo[8 * nx + i] = 0.5 * th; mo[9 * nx + i] = 0.5 * th;
+  mo[i] = n; mo[nx + i] = ux; mo[2 * nx + i] = uy; mo[3 * nx + i] = (pxx + pyy + th) / (3.0 * n);
+  mo[4 * nx + i] = qx; mo[5 * nx + i] = qy_; mo[6 * nx + i] = pxx; mo[7 * nx + i] = pxy;
+  mo[8 * nx + i] = two ? pyy : 0.5 * th; mo[9 * nx + i] = two ? th : 0.5 * th;
 }
 
-template <int RM>
+template <int RM, int D>
 static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++) {
-    hipLaunchKernelGGL((k_r1_stage<1, RM>), dim3(nblocks), dim3(512), 0, s, cases, m);
-    hipLaunchKernelGGL((k_r1_stage<2, RM>), dim3(nblocks), dim3(512), 0, s, cases, m);
-    hipLaunchKernelGGL((k_r1_stage<3, RM>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<1, RM, D>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<2, RM, D>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<3, RM, D>), dim3(nblocks), dim3(512), 0, s, cases, m);
   }
 }
 
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, long nsteps, hipStream_t s) {
+int r1_tile(int rmax) { return rmax <= 128 ? R1_TILE : R1_TILE_2; }
+
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, long nsteps,
+                          hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  if (rmax > 4 * MAXQH) return hipErrorInvalidValue;
   const int2 *m = (const int2 *)map;
-  if (rmax <= 64) r1_steps<64>(cases, m, nblocks, nsteps, s);
-  else r1_steps<4 * MAXQH>(cases, m, nblocks, nsteps, s);
+  if (dim == 1) {
+    if (rmax <= 64) r1_steps<64, 1>(cases, m, nblocks, nsteps, s);
+    else if (rmax <= 4 * MAXQH) r1_steps<4 * MAXQH, 1>(cases, m, nblocks, nsteps, s);
+    else return hipErrorInvalidValue;
+  } else if (dim == 2) {
+    if (rmax <= 128) r1_steps<128, 2>(cases, m, nblocks, nsteps, s);
+    else if (rmax <= R1_RMAX) r1_steps<R1_RMAX, 2>(cases, m, nblocks, nsteps, s);
+    else return hipErrorInvalidValue;
+  } else {
+    return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

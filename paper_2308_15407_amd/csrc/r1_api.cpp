@@ -1,8 +1,9 @@
-// r1_api.cpp -- host side of the reduced 1D model of the Fourier flow
-// (Sec. II.B, 1D flows): phi and theta on the 2 qx_half x-nodes, advanced by
-// one fused kernel per TVD-RK3 stage (k_r1_stage).  The lattice, the grid and
-// the finite-difference weights come from the same case construction as the
-// 3D path; the y and z velocity sets are not used.
+// r1_api.cpp -- host side of the reduced models (Sec. II.B): phi and theta on
+// the 2 qx_half x-nodes (1D flows: the Fourier flow) or on the 2 qx_half x qy
+// (x, y) nodes (2D flows: Couette and Poiseuille), advanced by one fused
+// kernel per TVD-RK3 stage (k_r1_stage).  The lattice, the grid and the
+// finite-difference weights come from the same case construction as the 3D
+// path; the z velocity set (and the y set in 1D) is not used.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,51 +30,77 @@ struct fdlb_r1_ctx {
   R1Dev *d_cases = nullptr;
   int *d_map = nullptr;
   int nmap = 0;
-  int rmax = 0;    // the largest row count (4 qx_half) of the cases
+  int rmax = 0;    // the largest row count of the cases
+  int dim = 0;     // 1 or 2, the same for every case
+  int tile = R1_TILE;
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// dimension of the reduced model of a case: the Fourier flow is 1D, the
+// Couette and Poiseuille flows 2D
+static int r1_dim(const fdlb_params &p) { return p.flow == 0 ? 1 : 2; }
+static int r1_rows(const CaseHost &c, int dim) { return 4 * c.qh * (dim == 2 ? c.qy : 1); }
+
 // the parameters the reduced model accepts, and the case built from them
 static int r1_case(const fdlb_params &p, CaseHost &c, std::string &why) {
-  if (p.qx_half > MAXQH) { why = "reduced 1D model: qx_half must be in [1, 32]"; return -1; }
-  if (p.uy_left != 0 || p.uy_right != 0 || p.uy_init != 0 || p.ay != 0) {
-    why = "reduced 1D model: no y-motion (walls, initial state) and no body force";
+  const int dim = r1_dim(p);
+  if (p.qx_half > MAXQH) { why = "reduced model: qx_half must be in [1, 32]"; return -1; }
+  if (dim == 1 && (p.uy_left != 0 || p.uy_right != 0 || p.uy_init != 0 || p.ay != 0)) {
+    why = "reduced 1D model (Fourier flow): no y-motion (walls, initial state) and no body force";
     return -1;
   }
-  if (p.chi_mode != 0) { why = "reduced 1D model: local contact value only (chi_mode 0)"; return -1; }
-  if (p.precision != FDLB_F64) { why = "reduced 1D model: FP64 storage only"; return -1; }
+  if (dim == 2 && 4 * p.qx_half * p.qy > R1_RMAX) { why = "reduced 2D model: 4 qx_half qy must be <= 256"; return -1; }
+  if (p.chi_mode != 0) { why = "reduced model: local contact value only (chi_mode 0)"; return -1; }
+  if (p.precision != FDLB_F64) { why = "reduced model: FP64 storage only"; return -1; }
   fdlb_params q = p;
-  q.qy = 2; q.qz = 2;   // the transverse sets of the shared construction (unused here)
+  if (dim == 1) q.qy = 2;
+  q.qz = 2;   // transverse sets of the shared construction that are not used here
   return build_case(q, c, why);
 }
 
 // bytes of one case's arrays: lattice, 1/dx, wall rows, f / g1 / g2, moments
 static size_t r1_case_bytes(const CaseHost &c) {
-  const size_t R = 4 * c.qh;
+  const size_t R = r1_rows(c, r1_dim(c.p));
   return al256(sizeof(double) * c.lat.size()) + al256(sizeof(double) * c.nx) + al256(sizeof(double) * 2 * R) +
          3 * al256(sizeof(double) * R * c.nx) + al256(sizeof(double) * FDLB_NMOM * c.nx);
 }
 
-static size_t r1_tiles(const CaseHost &c) { return (c.nx + R1_TILE - 1) / R1_TILE; }
+static size_t r1_tiles(const CaseHost &c, int tile) { return (c.nx + tile - 1) / tile; }
 
-// phi and theta of the state with fields (n, u_x, T, q_x) per cell: the
-// Grad-13-type distribution integrated over p_y and p_z,
-//   phi = n Proj[g (1 + s xi (xi^2/T - 3))], theta = 2T n Proj[g (1 + s xi (xi^2/T - 1))],
-// s = q_x / (5 n T^2), optionally times (1 + noise) node by node
+// phi and theta of the state with fields (n, u_x, u_y, T, q_x, P_xy) per
+// cell: the Grad-13-type distribution integrated over the dropped axes, with
+// s = q_x / (5 n T^2):
+//   1D: phi = n Proj[g (1 + s xi (xi^2/T - 3))], theta = 2T n Proj[g (1 + s xi (xi^2/T - 1))]
+//   2D: phi = n Proj[g (1 + P_xy xi_x xi_y/(n T^2) + s xi_x ((xi_x^2 + xi_y^2)/T - 4))],
+//       theta = T n Proj[g (1 + P_xy xi_x xi_y/(n T^2) + s xi_x ((xi_x^2 + xi_y^2)/T - 2))]
+// optionally times (1 + noise) node by node
 static void r1_fill(const CaseHost &c, const double *fields, const double *noise, std::vector<double> &f) {
-  const int nx = c.nx, Q = c.qh, Q2 = 2 * Q, R = 4 * Q;
-  f.assign((size_t)R * nx, 0.0);
-  std::vector<double> X[4];
-  for (int a = 0; a < 4; a++) X[a].assign(Q2, 0.0);
+  const int dim = r1_dim(c.p), nx = c.nx, Q = c.qh, Q2 = 2 * Q, qy = dim == 2 ? c.qy : 1, Kh = Q2 * qy;
+  f.assign((size_t)2 * Kh * nx, 0.0);
+  std::vector<double> X[4], Y[4];
+  for (int a = 0; a < 4; a++) { X[a].assign(Q2, 0.0); Y[a].assign(qy, 0.0); }
   for (int i = 0; i < nx; i++) {
-    const double n = fields[i], ux = fields[nx + i], T = fields[3 * nx + i], qx = fields[4 * nx + i];
+    const double n = fields[i], ux = fields[nx + i], uy = fields[2 * nx + i], T = fields[3 * nx + i];
+    const double qx = fields[4 * nx + i], pxy = fields[5 * nx + i];
     for (int a = 0; a < 4; a++) host_half_table(c.lat.data(), c.lo, Q, ux, T, a, X[a].data());
     const double s = qx / (5.0 * n * T * T);
-    for (int k = 0; k < Q2; k++) {
-      f[(size_t)k * nx + i] = n * (X[0][k] - 3.0 * s * X[1][k] + s / T * X[3][k]);
-      f[(size_t)(Q2 + k) * nx + i] = 2.0 * T * n * (X[0][k] - s * X[1][k] + s / T * X[3][k]);
+    if (dim == 1) {
+      for (int k = 0; k < Q2; k++) {
+        f[(size_t)k * nx + i] = n * (X[0][k] - 3.0 * s * X[1][k] + s / T * X[3][k]);
+        f[(size_t)(Q2 + k) * nx + i] = 2.0 * T * n * (X[0][k] - s * X[1][k] + s / T * X[3][k]);
+      }
+      continue;
     }
+    for (int b = 0; b < 4; b++) host_full_table(&c.lat[c.lo.Hy], qy, uy, T, b, Y[b].data());
+    const double sxy = pxy / (n * T * T);
+    for (int kx = 0; kx < Q2; kx++)
+      for (int ky = 0; ky < qy; ky++) {
+        const double base = X[0][kx] * Y[0][ky] + sxy * X[1][kx] * Y[1][ky] + s / T * X[3][kx] * Y[0][ky] +
+                            s / T * X[1][kx] * Y[2][ky];
+        f[(size_t)(kx * qy + ky) * nx + i] = n * (base - 4.0 * s * X[1][kx] * Y[0][ky]);
+        f[(size_t)(Kh + kx * qy + ky) * nx + i] = T * n * (base - 2.0 * s * X[1][kx] * Y[0][ky]);
+      }
   }
   if (noise)
     for (size_t j = 0; j < f.size(); j++) f[j] *= 1.0 + noise[j];
@@ -86,8 +113,12 @@ extern "C" size_t fdlb_r1_workspace_bytes(const fdlb_params *cases, int ncases) 
     CaseHost c;
     std::string why;
     if (r1_case(cases[i], c, why)) { api_fail(FDLB_EINVAL, "case " + std::to_string(i) + ": " + why); return 0; }
+    if (r1_dim(cases[i]) != r1_dim(cases[0])) {
+      api_fail(FDLB_EINVAL, "reduced model: a batch holds cases of one dimension (Fourier, or Couette/Poiseuille)");
+      return 0;
+    }
     total += r1_case_bytes(c);
-    tiles += r1_tiles(c);
+    tiles += r1_tiles(c, R1_TILE_2);   // the smaller tile bounds the map
   }
   return total + al256(sizeof(int) * 2 * tiles);
 }
@@ -110,16 +141,22 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
   h->d_cases = (R1Dev *)take(sizeof(R1Dev) * ncases);
   std::vector<int> map;
   auto bail = [&](int code) { delete h; return code; };
+  h->dim = r1_dim(cases[0]);
   for (int i = 0; i < ncases; i++) {
     CaseHost &c = h->cases[i];
     std::string why;
     if (r1_case(cases[i], c, why)) return bail(api_fail(FDLB_EINVAL, why));
-    const int nx = c.nx, Q = c.qh, Q2 = 2 * Q, R = 4 * Q;
-    h->rmax = std::max(h->rmax, R);
+    h->rmax = std::max(h->rmax, r1_rows(c, h->dim));
+  }
+  h->tile = r1_tile(h->rmax);
+  for (int i = 0; i < ncases; i++) {
+    CaseHost &c = h->cases[i];
+    const int nx = c.nx, Q = c.qh, Q2 = 2 * Q, qy = h->dim == 2 ? c.qy : 1, Kh = Q2 * qy, R = 2 * Kh;
     R1Dev &d = h->hdev[i];
     memset(&d, 0, sizeof(d));
-    d.nx = nx; d.qh = Q; d.R = R;
-    d.collision = c.p.collision; d.pr_fixed = c.p.pr_fixed; d.eta0 = c.p.eta0; d.dt = c.dt;
+    d.nx = nx; d.qh = Q; d.qy = qy; d.R = R; d.dim = h->dim;
+    d.collision = c.p.collision; d.j1_shear = c.p.j1_shear; d.pr_fixed = c.p.pr_fixed; d.eta0 = c.p.eta0;
+    d.dt = c.dt; d.ay = c.p.ay;
     d.tau_pre = c.p.kn > 0 ? 5.0 * sqrt(2.0 * M_PI) / 16.0 * c.p.kn * c.chi0 : 0.0;
     d.lo = c.lo;
     double *lat = (double *)take(sizeof(double) * c.lat.size());
@@ -130,30 +167,37 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
     d.g2 = (double *)take(sizeof(double) * R * nx);
     d.mom = (double *)take(sizeof(double) * FDLB_NMOM * nx);
     d.lat = lat; d.invdx = invdx; d.gw = gw;
-    // wall rows at n = 1: phi_w = Proj[g(0, T_w)], theta_w = 2 T_w phi_w;
+    // wall rows at n = 1: phi_w = Proj[g(0, T_w)] (times Proj[g(U_w, T_w)] on
+    // the y-nodes in 2D), theta_w = 2 T_w phi_w (1D) or T_w phi_w (2D);
     // wallD = the emitted mass flux per unit n_w
-    std::vector<double> hgw(2 * R), X(Q2);
+    std::vector<double> hgw(2 * R), X(Q2), Y(qy, 1.0);
     for (int w = 0; w < 2; w++) {
-      const double Tw = w == 0 ? c.p.t_left : c.p.t_right;
+      const double Tw = w == 0 ? c.p.t_left : c.p.t_right, Uw = w == 0 ? c.p.uy_left : c.p.uy_right;
       host_half_table(c.lat.data(), c.lo, Q, 0.0, Tw, 0, X.data());
+      if (h->dim == 2) host_full_table(&c.lat[c.lo.Hy], qy, Uw, Tw, 0, Y.data());
+      const double tf = h->dim == 2 ? Tw : 2.0 * Tw;
       double D = 0.0;
-      for (int k = 0; k < Q2; k++) {
-        hgw[w * R + k] = X[k];
-        hgw[w * R + Q2 + k] = 2.0 * Tw * X[k];
-        const double p = c.lat[c.lo.px + k];
-        if ((w == 0) == (p > 0.0)) D += p * X[k];
-      }
+      for (int kx = 0; kx < Q2; kx++)
+        for (int ky = 0; ky < qy; ky++) {
+          const double v = X[kx] * Y[ky];
+          hgw[w * R + kx * qy + ky] = v;
+          hgw[w * R + Kh + kx * qy + ky] = tf * v;
+          const double p = c.lat[c.lo.px + kx];
+          if ((w == 0) == (p > 0.0)) D += p * v;
+        }
       d.wallD[w] = D;
     }
     R1CHK(hipMemcpyAsync(lat, c.lat.data(), sizeof(double) * c.lat.size(), hipMemcpyHostToDevice, h->stream));
     R1CHK(hipMemcpyAsync(invdx, c.invdx.data(), sizeof(double) * nx, hipMemcpyHostToDevice, h->stream));
     R1CHK(hipMemcpyAsync(gw, hgw.data(), sizeof(double) * 2 * R, hipMemcpyHostToDevice, h->stream));
     std::vector<double> fields((size_t)6 * nx, 0.0), f;
-    for (int k = 0; k < nx; k++) { fields[k] = c.p.n_init; fields[3 * nx + k] = c.p.t_init; }
+    for (int k = 0; k < nx; k++) {
+      fields[k] = c.p.n_init; fields[2 * nx + k] = h->dim == 2 ? c.p.uy_init : 0.0; fields[3 * nx + k] = c.p.t_init;
+    }
     r1_fill(c, fields.data(), nullptr, f);
     R1CHK(hipMemcpyAsync(d.f, f.data(), sizeof(double) * f.size(), hipMemcpyHostToDevice, h->stream));
     R1CHK(hipStreamSynchronize(h->stream));
-    for (size_t t = 0; t < r1_tiles(c); t++) { map.push_back(i); map.push_back((int)t); }
+    for (size_t t = 0; t < r1_tiles(c, h->tile); t++) { map.push_back(i); map.push_back((int)t); }
   }
   h->d_map = (int *)take(sizeof(int) * map.size());
   h->nmap = (int)(map.size() / 2);
@@ -167,7 +211,7 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
 
 extern "C" int fdlb_r1_step(fdlb_r1_handle h, long nsteps) {
   if (!h || nsteps < 0) return api_fail(FDLB_EINVAL, "null handle or negative step count");
-  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, nsteps, h->stream));
+  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, h->dim, nsteps, h->stream));
   return FDLB_OK;
 }
 
@@ -195,7 +239,8 @@ extern "C" int fdlb_r1_set_state(fdlb_r1_handle h, int c, const double *fields, 
 extern "C" int fdlb_r1_get_f(fdlb_r1_handle h, int c, double *host_f) {
   if (!h || c < 0 || c >= (int)h->cases.size() || !host_f) return api_fail(FDLB_EINVAL, "bad handle, case or output");
   const CaseHost &ch = h->cases[c];
-  R1CHK(hipMemcpyAsync(host_f, h->hdev[c].f, sizeof(double) * 4 * ch.qh * ch.nx, hipMemcpyDeviceToHost, h->stream));
+  R1CHK(hipMemcpyAsync(host_f, h->hdev[c].f, sizeof(double) * h->hdev[c].R * ch.nx, hipMemcpyDeviceToHost,
+                       h->stream));
   R1CHK(hipStreamSynchronize(h->stream));
   return FDLB_OK;
 }

@@ -112,8 +112,10 @@ class Solver:
 
 
 class ReducedSolver:
-    """A batch of Fourier cases in the paper's reduced 1D form: phi and theta
-    on the 2 qx_half x-nodes (include/fdlb.h, fdlb_r1_*), FP64."""
+    """A batch of cases in the paper's reduced form (include/fdlb.h, fdlb_r1_*),
+    FP64: Fourier cases as phi and theta on the 2 qx_half x-nodes (1D),
+    Couette and Poiseuille cases on the 2 qx_half x qy (x, y) nodes (2D); one
+    dimension per batch."""
 
     def __init__(self, cases, device="cuda:0", stream=None):
         if isinstance(cases, dict):
@@ -128,7 +130,7 @@ class ReducedSolver:
             self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
             self.handle = F.fdlb_r1_init(self.cases, self.workspace.data_ptr(), nbytes, self.stream.cuda_stream)
         self.nx = [c["nx"] for c in self.cases]
-        self.rows = [4 * c["qx_half"] for c in self.cases]
+        self.rows = [4 * c["qx_half"] * (c.get("qy", 3) if c.get("flow", 0) != 0 else 1) for c in self.cases]
 
     @property
     def ncases(self):
@@ -158,7 +160,7 @@ class ReducedSolver:
         F.fdlb_r1_set_state(self.handle, c, fields, noise)
 
     def get_f(self, c=0):
-        """[4 qx_half][nx]: phi rows, then theta rows."""
+        """[rows][nx]: phi rows (kx qy + ky in 2D), then theta rows."""
         return F.fdlb_r1_get_f(self.handle, c, self.rows[c], self.nx[c])
 
     def dt(self, c=0):
