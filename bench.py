@@ -147,19 +147,20 @@ def sweep_r1_leg(steps, retune, ncases=1024):
             "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}}
 
 
-def reduced_leg(steps, warmup=5):
-    """The paper's reduced 1D model (phi, theta on the 2 Q_x^h x-nodes) of the
-    Fourier workload Nx=32768, Q_x^h=16 (BGK + J1, FP64): 4 Q_x^h = 64 rows per
-    cell against the 3D lattice's K = 512 (the large_case_f64 leg).  A step is
-    three launches of the fused stage kernel; its algorithmic bytes are eight
-    passes over the rows (each stage reads its input and writes its output,
-    stages 2 and 3 also read f^n) of 8 B each."""
+def reduced_leg(steps, workload="R2", warmup=5):
+    """A workload in the paper's reduced form, FP64: R2 (Fourier, Nx=32768,
+    Q_x^h=16) as the 1D model, 64 rows per cell against the 3D lattice's K = 512
+    (the large_case_f64 leg); C2 (Couette, Nx=256) as the 2D model, 2 x 16 x 4
+    x 2 = 128 rows per cell against K = 256 (the main line).  A step is three
+    launches of the fused stage kernel; its algorithmic bytes are eight passes
+    over the rows (each stage reads its input and writes its output, stages 2
+    and 3 also read f^n) of 8 B each."""
     import torch
     import fdlb_inputs as I
     from paper_2308_15407_amd.solver import ReducedSolver
-    cfg = I.config("R2", precision=0)
+    cfg = I.config(workload, precision=0)
     s = ReducedSolver(cfg)
-    vals = 4 * cfg["qx_half"] * cfg["nx"]
+    vals = s.rows[0] * cfg["nx"]
     s.step(warmup)
     s.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -169,7 +170,9 @@ def reduced_leg(steps, warmup=5):
     b.synchronize()
     ms = a.elapsed_time(b) / steps
     eff = 8 * 8 * vals / (ms * 1e-3) / 1e9
-    return {"workload": "reduced 1D Fourier Nx=32768 uniform, phi/theta on 2x16 x-nodes (64 rows), FP64",
+    names = {"R2": "reduced 1D Fourier Nx=32768 uniform, phi/theta on 2x16 x-nodes (64 rows), FP64",
+             "C2": "reduced 2D Couette Nx=256 tanh-stretched, phi/theta on 2x8 x 4 (x, y) nodes (128 rows), FP64"}
+    return {"workload": names.get(workload, workload),
             "value": round(vals / (ms * 1e-3), 1), "unit": "row-cell updates/s", "ms_per_step": round(ms, 5),
             "values": vals, "effective_GBps_whole_step": round(eff, 1), "frac_of_hbm_peak": round(eff / HBM_PEAK_GBS, 4)}
 
@@ -253,7 +256,8 @@ def main():
                 "tiling": {"kx_per_chunk": tileL[0], "waves": tileL[1]},
                 "roofline": roofline(profL, nodesL, prec, "k_update<%s,2>" % ("double" if prec == 0 else "float"), "R2"),
                 "kernel_ms": {"table": round(profL[0], 5), "update": [round(x, 5) for x in profL[1 + 3 * prec:4 + 3 * prec]]}}
-        out["reduced_1d"] = reduced_leg(args.large_steps)
+        out["reduced_1d"] = reduced_leg(args.large_steps, "R2")
+        out["reduced_2d"] = reduced_leg(args.steps, "C2", warmup=args.warmup)
         out["sweep"] = sweep_leg(args.sweep_steps, args.retune)
         out["sweep_r1"] = sweep_r1_leg(args.r1_steps, args.retune)
         out["time_to_steady"] = time_to_steady_leg(args.tts_batch, args.tts_seq)

@@ -46,11 +46,11 @@ enum {
 // kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
 // reduced models: nsteps TVD-RK3 steps of every case (map: int2 {case, tile}
-// per block of r1_tile(rmax) cells; rmax: the largest row count of the cases;
-// dim: 1 or 2, the same for every case), and the moments of case c into its
-// mom array
-int r1_tile(int rmax);
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, long nsteps,
+// per block of `tile` = r1_tile(rmax, total cells) cells; rmax: the largest
+// row count of the cases; dim: 1 or 2, the same for every case), and the
+// moments of case c into its mom array
+int r1_tile(int rmax, int total_cells);
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile, long nsteps,
                           hipStream_t s);
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
 // wide: the map may hold cases with qx_half > MAXQH (adds the wide pass);

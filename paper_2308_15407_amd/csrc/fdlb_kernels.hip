@@ -1294,11 +1294,10 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 // row of its cells: WENO-5 advection with the diffuse-wall rules of the 3D
 // pass, the body force on the y-nodes (2D), relaxation and the TVD-RK3
 // combination (eq:rk3).  D is the dimension of the reduced model, RM the
-// largest row count of the launch (it sizes the LDS; TS = 32 cells up to 128
-// rows, 16 above).
-template <int STAGE, int RM, int D>
+// largest row count of the launch (it sizes the LDS) and TS the cells per
+// block (32 up to 128 rows, 16 above, 8 on small maps).
+template <int STAGE, int RM, int D, int TS>
 __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
-  constexpr int TS = RM <= 128 ? R1_TILE : R1_TILE_2;
   constexpr int W = TS + 2 * R1_HALO, QYM = D == 2 ? MAXQY : 1;
   const int2 bm = map[blockIdx.x];
   const R1Dev &c = cases[bm.x];
@@ -1624,33 +1623,43 @@ __global__ void k_r1_moments(const R1Dev *__restrict__ cases, int c_idx) {
   mo[8 * nx + i] = two ? pyy : 0.5 * th; mo[9 * nx + i] = two ? th : 0.5 * th;
 }
 
-template <int RM, int D>
+template <int RM, int D, int TS>
 static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++) {
-    hipLaunchKernelGGL((k_r1_stage<1, RM, D>), dim3(nblocks), dim3(512), 0, s, cases, m);
-    hipLaunchKernelGGL((k_r1_stage<2, RM, D>), dim3(nblocks), dim3(512), 0, s, cases, m);
-    hipLaunchKernelGGL((k_r1_stage<3, RM, D>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<1, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<2, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    hipLaunchKernelGGL((k_r1_stage<3, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
   }
 }
 
-int r1_tile(int rmax) { return rmax <= 128 ? R1_TILE : R1_TILE_2; }
+// cells per block: 32 up to 128 rows, 16 above; maps that would have at most
+// SMALL_TABLE_MAP blocks take CTILE_SMALL cells per block (latency-bound sizes)
+int r1_tile(int rmax, int total_cells) {
+  const int t = rmax <= 128 ? R1_TILE : R1_TILE_2;
+  return (total_cells + t - 1) / t <= SMALL_TABLE_MAP ? CTILE_SMALL : t;
+}
 
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, long nsteps,
+template <int RM, int D>
+static hipError_t r1_by_tile(const R1Dev *cases, const int2 *m, int nblocks, int tile, long nsteps, hipStream_t s) {
+  constexpr int TL = RM <= 128 ? R1_TILE : R1_TILE_2;
+  if (tile == TL) r1_steps<RM, D, TL>(cases, m, nblocks, nsteps, s);
+  else if (tile == CTILE_SMALL) r1_steps<RM, D, CTILE_SMALL>(cases, m, nblocks, nsteps, s);
+  else return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile, long nsteps,
                           hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
   const int2 *m = (const int2 *)map;
   if (dim == 1) {
-    if (rmax <= 64) r1_steps<64, 1>(cases, m, nblocks, nsteps, s);
-    else if (rmax <= 4 * MAXQH) r1_steps<4 * MAXQH, 1>(cases, m, nblocks, nsteps, s);
-    else return hipErrorInvalidValue;
+    if (rmax <= 64) return r1_by_tile<64, 1>(cases, m, nblocks, tile, nsteps, s);
+    if (rmax <= 4 * MAXQH) return r1_by_tile<4 * MAXQH, 1>(cases, m, nblocks, tile, nsteps, s);
   } else if (dim == 2) {
-    if (rmax <= 128) r1_steps<128, 2>(cases, m, nblocks, nsteps, s);
-    else if (rmax <= R1_RMAX) r1_steps<R1_RMAX, 2>(cases, m, nblocks, nsteps, s);
-    else return hipErrorInvalidValue;
-  } else {
-    return hipErrorInvalidValue;
+    if (rmax <= 128) return r1_by_tile<128, 2>(cases, m, nblocks, tile, nsteps, s);
+    if (rmax <= R1_RMAX) return r1_by_tile<R1_RMAX, 2>(cases, m, nblocks, tile, nsteps, s);
   }
-  return hipGetLastError();
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s) {

@@ -118,7 +118,7 @@ extern "C" size_t fdlb_r1_workspace_bytes(const fdlb_params *cases, int ncases) 
       return 0;
     }
     total += r1_case_bytes(c);
-    tiles += r1_tiles(c, R1_TILE_2);   // the smaller tile bounds the map
+    tiles += r1_tiles(c, CTILE_SMALL);   // the smallest tile bounds the map
   }
   return total + al256(sizeof(int) * 2 * tiles);
 }
@@ -142,13 +142,15 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
   std::vector<int> map;
   auto bail = [&](int code) { delete h; return code; };
   h->dim = r1_dim(cases[0]);
+  int cells = 0;
   for (int i = 0; i < ncases; i++) {
     CaseHost &c = h->cases[i];
     std::string why;
     if (r1_case(cases[i], c, why)) return bail(api_fail(FDLB_EINVAL, why));
     h->rmax = std::max(h->rmax, r1_rows(c, h->dim));
+    cells += c.nx;
   }
-  h->tile = r1_tile(h->rmax);
+  h->tile = r1_tile(h->rmax, cells);
   for (int i = 0; i < ncases; i++) {
     CaseHost &c = h->cases[i];
     const int nx = c.nx, Q = c.qh, Q2 = 2 * Q, qy = h->dim == 2 ? c.qy : 1, Kh = Q2 * qy, R = 2 * Kh;
@@ -211,7 +213,7 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
 
 extern "C" int fdlb_r1_step(fdlb_r1_handle h, long nsteps) {
   if (!h || nsteps < 0) return api_fail(FDLB_EINVAL, "null handle or negative step count");
-  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, h->dim, nsteps, h->stream));
+  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, h->dim, h->tile, nsteps, h->stream));
   return FDLB_OK;
 }
 

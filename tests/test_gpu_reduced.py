@@ -145,3 +145,17 @@ def test_reduced_2d_batch_matches_single_bitwise_and_conserves_mass():
         assert np.array_equal(b.get_f(i), s.get_f(0)), i
         x, jac = F.fdlb_case_grid(cfgs[i])
         assert abs(np.sum(b.moments(i)[0] * jac) - np.sum(m0[i] * jac)) < 1e-13 * np.sum(m0[i] * jac), i
+
+
+@pytest.mark.parametrize("cfg,steps,two", [
+    # maps beyond 32 blocks take the large tiles: 32 cells (up to 128 rows) and 16 (above)
+    (_fourier(nx=1100, qx_half=4, kn=0.05, eta0=0.1, collision=I.SHAKHOV_DENSE), 3, False),
+    (dict(I.BASE, flow=I.COUETTE, nx=1100, qx_half=4, qy=3, kn=0.05, eta0=0.1, uy_left=-0.3, uy_right=0.3), 3, True),
+    (dict(I.BASE, flow=I.POISEUILLE, nx=600, qx_half=8, qy=5, kn=0.05, eta0=0.15, ay=0.05,
+          collision=I.SHAKHOV_DENSE), 2, True),
+])
+def test_reduced_models_with_large_tiles_match_oracle(cfg, steps, two):
+    s, o = (_pair2 if two else _pair)(cfg, 160 + cfg["nx"])
+    s.step(steps)
+    o.step(steps)
+    (_compare2 if two else _compare)(s, o, "large tiles %s nx=%d" % ("2D" if two else "1D", cfg["nx"]))
