@@ -232,8 +232,9 @@ void fdlb_destroy(fdlb_handle h);
      int p_z^2 f dp_z on the 2 qx_half x qy (x, y) nodes (eq:evolution_2D with
      the body force, moments eq:macro2D), 4 qx_half qy <= 256.  Rows: phi
      (kx, ky) at kx qy + ky, then theta in the same order.
-   Every case: chi_mode 0, precision FDLB_F64, qx_half <= 32; qz is ignored;
-   one dimension per batch.  State layout: [rows][nx] doubles, x-nodes in
+   Every case: precision FDLB_F64, qx_half <= 32; chi_mode 0 or 1 (the
+   revised Enskog average, by its own pass over the phi rows before each
+   stage; nx <= 4000); qz is ignored; one dimension per batch.  State layout: [rows][nx] doubles, x-nodes in
    the order of fdlb_case_lattice's, cells contiguous.  Each TVD-RK3 step is
    three launches of one fused kernel; the calls follow the 3D solver's
    conventions (caller-owned workspace, stream, error codes). */

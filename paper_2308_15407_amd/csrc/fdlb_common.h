@@ -116,6 +116,9 @@ struct R1Dev {
   double wallD[2];      // sum over the emitted phi rows of p_x g^w (left, right)
   double *f, *g1, *g2;  // [R][nx] f^n and the two RK stage states
   double *mom;          // [FDLB_NMOM][nx]
+  int chi_mode;         // 0: chi(eta0 n); 1: chi(eta0 nbar), the revised Enskog average
+  double sigma;         // molecular diameter (chi_mode 1)
+  double *nbar;         // [nx] average density of the stage input (chi_mode 1)
 };
 
 // ---------------------------------------------------------------------------

@@ -50,8 +50,10 @@ enum {
 // row count of the cases; dim: 1 or 2, the same for every case), and the
 // moments of case c into its mom array
 int r1_tile(int rmax, int total_cells);
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile, long nsteps,
-                          hipStream_t s);
+// (map_n: int2 {case, tile} per NBAR_TILE cells of the chi_mode 1 cases, with
+// lds_n the bytes of the largest window of a tile; nblocks_n = 0 if none)
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile,
+                          const int *map_n, int nblocks_n, size_t lds_n, long nsteps, hipStream_t s);
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
 // wide: the map may hold cases with qx_half > MAXQH (adds the wide pass);
 // tile: the cells per block the map was built with (CTILE or CTILE_SMALL)

@@ -1285,6 +1285,51 @@ hipError_t launch_copy_probe(const void *src, void *dst, size_t bytes, hipStream
 // ---------------------------------------------------------------------------
 // reduced models (Sec. II.B): one fused kernel per RK stage
 // ---------------------------------------------------------------------------
+// Revised Enskog average density of reduced cases (chi_mode 1): the window
+// sums of k_nbar, with the density of each window cell summed over the phi
+// rows of the stage input.  One 8-wave block per NBAR_TILE cells.
+__global__ void __launch_bounds__(512) k_r1_nbar(const R1Dev *__restrict__ cases, const int2 *__restrict__ map,
+                                                 int stage) {
+  extern __shared__ double s_n[];   // densities [nwin] and faces [nwin + 1] of the tile's window
+  __shared__ double s_x[NBAR_TILE];
+  __shared__ int s_lo[NBAR_TILE], s_hi[NBAR_TILE];
+  const int2 bm = map[blockIdx.x];
+  const R1Dev &c = cases[bm.x];
+  const int nx = c.nx, c0 = bm.y * NBAR_TILE, c1 = min(c0 + NBAR_TILE, nx), Kh = 2 * c.qh * c.qy;
+  const double *lat = c.lat;
+  const int jmin = (int)lat[c.lo.wlo + c0], jmax = (int)lat[c.lo.whi + c1 - 1];
+  const int nwin = jmax - jmin + 1;
+  double *s_f = s_n + nwin;
+  const double *gin = stage == 1 ? c.f : (stage == 2 ? c.g1 : c.g2);
+  const int tid = threadIdx.x;
+  if (tid < c1 - c0) {
+    s_x[tid] = lat[c.lo.xcn + c0 + tid];
+    s_lo[tid] = (int)lat[c.lo.wlo + c0 + tid];
+    s_hi[tid] = (int)lat[c.lo.whi + c0 + tid];
+  }
+  for (int q = tid; q <= nwin; q += blockDim.x) s_f[q] = lat[c.lo.xf + jmin + q];
+  for (int q = tid; q < nwin; q += blockDim.x) {
+    double a = 0.0;
+    for (int r = 0; r < Kh; r++) a += gin[(size_t)r * nx + jmin + q];
+    s_n[q] = a;
+  }
+  __syncthreads();
+  const int lane = tid & 63, wv = tid >> 6, nwv = blockDim.x >> 6;
+  const double sg = c.sigma, s2 = sg * sg;
+  for (int i = c0 + wv; i < c1; i += nwv) {
+    const double x = s_x[i - c0];
+    const int lo = s_lo[i - c0] - jmin, hi = s_hi[i - c0] - jmin;
+    double acc = 0.0;
+    for (int q = lo + lane; q <= hi; q += 64) {
+      const double a = fmax(s_f[q], x - sg) - x, b = fmin(s_f[q + 1], x + sg) - x;
+      acc += s_n[q] * ((s2 * b - b * b * b / 3.0) - (s2 * a - a * a * a / 3.0));
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if (lane == 0) c.nbar[i] = 3.0 / (4.0 * sg * s2) * acc;
+  }
+}
+
 // A block owns TS cells of one case.  It stages phi and theta of its cells and
 // a halo of R1_HALO cells per side in LDS, and then, without going back to
 // memory: the moments (eq:macro1D, eq:macro2D) of every staged cell, the wall
@@ -1364,7 +1409,9 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     if (live && sub == 0) {
       const double T_ = (pin + th) / (3.0 * n);
       s_m[0][wc] = n; s_m[1][wc] = ux; s_m[2][wc] = uy; s_m[3][wc] = T_; s_m[4][wc] = qx; s_m[5][wc] = qy_;
-      s_l[0][wc] = log(n); s_l[1][wc] = log(chi_cs(c.eta0 * n)); s_l[2][wc] = log(T_);
+      // revised Enskog cases take chi at the average density of the stage input
+      const double nc = c.chi_mode == 1 ? c.nbar[cell] : n;
+      s_l[0][wc] = log(n); s_l[1][wc] = log(chi_cs(c.eta0 * nc)); s_l[2][wc] = log(T_);
     }
   } else if (tid == 448 || tid == 480) {
     // impenetrability: the incoming phi rows reach the wall face through the
@@ -1410,7 +1457,8 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       g[q] = d * c.invdx[i];
     }
     const double n = s_m[0][li], uy = s_m[2][li], T_ = s_m[3][li], qx = s_m[4][li], qy_ = s_m[5][li];
-    const double eta = c.eta0 * n, chi = chi_cs(eta), brc = 4.0 * eta * chi;
+    // b rho stays local; chi enters tau, Pr, the J1 prefactor and dln chi
+    const double eta = c.eta0 * n, chi = chi_cs(c.chi_mode == 1 ? c.eta0 * c.nbar[i] : eta), brc = 4.0 * eta * chi;
     double tau = 0.0, itau = 0.0;
     if (c.tau_pre > 0.0) {
       tau = c.tau_pre / (n * sqrt(T_)) *
@@ -1624,10 +1672,14 @@ __global__ void k_r1_moments(const R1Dev *__restrict__ cases, int c_idx) {
 }
 
 template <int RM, int D, int TS>
-static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, long nsteps, hipStream_t s) {
+static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, const int2 *mn, int nn, size_t ldsn,
+                     long nsteps, hipStream_t s) {
   for (long k = 0; k < nsteps; k++) {
+    if (nn > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nn), dim3(512), ldsn, s, cases, mn, 1);
     hipLaunchKernelGGL((k_r1_stage<1, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    if (nn > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nn), dim3(512), ldsn, s, cases, mn, 2);
     hipLaunchKernelGGL((k_r1_stage<2, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
+    if (nn > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nn), dim3(512), ldsn, s, cases, mn, 3);
     hipLaunchKernelGGL((k_r1_stage<3, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
   }
 }
@@ -1640,24 +1692,26 @@ int r1_tile(int rmax, int total_cells) {
 }
 
 template <int RM, int D>
-static hipError_t r1_by_tile(const R1Dev *cases, const int2 *m, int nblocks, int tile, long nsteps, hipStream_t s) {
+static hipError_t r1_by_tile(const R1Dev *cases, const int2 *m, int nblocks, int tile, const int2 *mn, int nn,
+                             size_t ldsn, long nsteps, hipStream_t s) {
   constexpr int TL = RM <= 128 ? R1_TILE : R1_TILE_2;
-  if (tile == TL) r1_steps<RM, D, TL>(cases, m, nblocks, nsteps, s);
-  else if (tile == CTILE_SMALL) r1_steps<RM, D, CTILE_SMALL>(cases, m, nblocks, nsteps, s);
+  if (tile == TL) r1_steps<RM, D, TL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
+  else if (tile == CTILE_SMALL) r1_steps<RM, D, CTILE_SMALL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
   else return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile, long nsteps,
-                          hipStream_t s) {
+hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile,
+                          const int *map_n, int nblocks_n, size_t lds_n, long nsteps, hipStream_t s) {
   if (nblocks <= 0) return hipSuccess;
-  const int2 *m = (const int2 *)map;
+  if (nblocks_n > 0 && (lds_n == 0 || lds_n > NBAR_LDS_MAX)) return hipErrorInvalidValue;
+  const int2 *m = (const int2 *)map, *mn = (const int2 *)map_n;
   if (dim == 1) {
-    if (rmax <= 64) return r1_by_tile<64, 1>(cases, m, nblocks, tile, nsteps, s);
-    if (rmax <= 4 * MAXQH) return r1_by_tile<4 * MAXQH, 1>(cases, m, nblocks, tile, nsteps, s);
+    if (rmax <= 64) return r1_by_tile<64, 1>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
+    if (rmax <= 4 * MAXQH) return r1_by_tile<4 * MAXQH, 1>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
   } else if (dim == 2) {
-    if (rmax <= 128) return r1_by_tile<128, 2>(cases, m, nblocks, tile, nsteps, s);
-    if (rmax <= R1_RMAX) return r1_by_tile<R1_RMAX, 2>(cases, m, nblocks, tile, nsteps, s);
+    if (rmax <= 128) return r1_by_tile<128, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
+    if (rmax <= R1_RMAX) return r1_by_tile<R1_RMAX, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
   }
   return hipErrorInvalidValue;
 }

@@ -31,6 +31,9 @@ struct fdlb_r1_ctx {
   int *d_map = nullptr;
   int nmap = 0;
   int rmax = 0;    // the largest row count of the cases
+  int *d_mapN = nullptr;   // averaged-density blocks of the chi_mode 1 cases
+  int nN = 0;
+  size_t ldsN = 0;
   int dim = 0;     // 1 or 2, the same for every case
   int tile = R1_TILE;
 };
@@ -51,7 +54,6 @@ static int r1_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     return -1;
   }
   if (dim == 2 && 4 * p.qx_half * p.qy > R1_RMAX) { why = "reduced 2D model: 4 qx_half qy must be <= 256"; return -1; }
-  if (p.chi_mode != 0) { why = "reduced model: local contact value only (chi_mode 0)"; return -1; }
   if (p.precision != FDLB_F64) { why = "reduced model: FP64 storage only"; return -1; }
   fdlb_params q = p;
   if (dim == 1) q.qy = 2;
@@ -63,7 +65,8 @@ static int r1_case(const fdlb_params &p, CaseHost &c, std::string &why) {
 static size_t r1_case_bytes(const CaseHost &c) {
   const size_t R = r1_rows(c, r1_dim(c.p));
   return al256(sizeof(double) * c.lat.size()) + al256(sizeof(double) * c.nx) + al256(sizeof(double) * 2 * R) +
-         3 * al256(sizeof(double) * R * c.nx) + al256(sizeof(double) * FDLB_NMOM * c.nx);
+         3 * al256(sizeof(double) * R * c.nx) + al256(sizeof(double) * FDLB_NMOM * c.nx) +
+         (c.p.chi_mode == 1 ? al256(sizeof(double) * c.nx) : 0);
 }
 
 static size_t r1_tiles(const CaseHost &c, int tile) { return (c.nx + tile - 1) / tile; }
@@ -119,8 +122,9 @@ extern "C" size_t fdlb_r1_workspace_bytes(const fdlb_params *cases, int ncases) 
     }
     total += r1_case_bytes(c);
     tiles += r1_tiles(c, CTILE_SMALL);   // the smallest tile bounds the map
+    if (c.p.chi_mode == 1) tiles += r1_tiles(c, NBAR_TILE);
   }
-  return total + al256(sizeof(int) * 2 * tiles);
+  return total + al256(sizeof(int) * 2 * tiles) + 256;   // two map regions, each 256-byte aligned
 }
 
 extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_workspace, size_t bytes,
@@ -139,7 +143,7 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
   size_t off = 0;
   auto take = [&](size_t nbytes) { char *p = ws + off; off += al256(nbytes); return p; };
   h->d_cases = (R1Dev *)take(sizeof(R1Dev) * ncases);
-  std::vector<int> map;
+  std::vector<int> map, mapN;
   auto bail = [&](int code) { delete h; return code; };
   h->dim = r1_dim(cases[0]);
   int cells = 0;
@@ -168,6 +172,9 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
     d.g1 = (double *)take(sizeof(double) * R * nx);
     d.g2 = (double *)take(sizeof(double) * R * nx);
     d.mom = (double *)take(sizeof(double) * FDLB_NMOM * nx);
+    d.chi_mode = c.p.chi_mode;
+    d.sigma = c.sigma;
+    if (c.p.chi_mode == 1) d.nbar = (double *)take(sizeof(double) * nx);
     d.lat = lat; d.invdx = invdx; d.gw = gw;
     // wall rows at n = 1: phi_w = Proj[g(0, T_w)] (times Proj[g(U_w, T_w)] on
     // the y-nodes in 2D), theta_w = 2 T_w phi_w (1D) or T_w phi_w (2D);
@@ -200,11 +207,25 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
     R1CHK(hipMemcpyAsync(d.f, f.data(), sizeof(double) * f.size(), hipMemcpyHostToDevice, h->stream));
     R1CHK(hipStreamSynchronize(h->stream));
     for (size_t t = 0; t < r1_tiles(c, h->tile); t++) { map.push_back(i); map.push_back((int)t); }
+    if (c.p.chi_mode == 1) {
+      // averaged-density blocks: the LDS holds the densities and faces of a tile's window
+      for (int t = 0; t * NBAR_TILE < nx; t++) {
+        const int i0 = t * NBAR_TILE, i1 = std::min(i0 + NBAR_TILE, nx) - 1;
+        const size_t wlen = (size_t)(c.lat[c.lo.whi + i1] - c.lat[c.lo.wlo + i0]) + 1;
+        h->ldsN = std::max(h->ldsN, sizeof(double) * (2 * wlen + 1));
+        mapN.push_back(i); mapN.push_back(t);
+      }
+    }
   }
   h->d_map = (int *)take(sizeof(int) * map.size());
   h->nmap = (int)(map.size() / 2);
+  h->nN = (int)(mapN.size() / 2);
+  if (h->nN > 0) h->d_mapN = (int *)take(sizeof(int) * mapN.size());
   if (off > bytes) return bail(api_fail(FDLB_ENOMEM, "workspace layout exceeds the buffer"));
+  if (h->ldsN > NBAR_LDS_MAX) return bail(api_fail(FDLB_EINVAL, "revised Enskog window too wide for the LDS"));
   R1CHK(hipMemcpyAsync(h->d_map, map.data(), sizeof(int) * map.size(), hipMemcpyHostToDevice, h->stream));
+  if (h->nN > 0)
+    R1CHK(hipMemcpyAsync(h->d_mapN, mapN.data(), sizeof(int) * mapN.size(), hipMemcpyHostToDevice, h->stream));
   R1CHK(hipMemcpyAsync(h->d_cases, h->hdev.data(), sizeof(R1Dev) * ncases, hipMemcpyHostToDevice, h->stream));
   R1CHK(hipStreamSynchronize(h->stream));
   *out = h;
@@ -213,7 +234,8 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
 
 extern "C" int fdlb_r1_step(fdlb_r1_handle h, long nsteps) {
   if (!h || nsteps < 0) return api_fail(FDLB_EINVAL, "null handle or negative step count");
-  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, h->dim, h->tile, nsteps, h->stream));
+  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, h->dim, h->tile, h->d_mapN, h->nN, h->ldsN, nsteps,
+                       h->stream));
   return FDLB_OK;
 }
 

@@ -159,3 +159,19 @@ def test_reduced_models_with_large_tiles_match_oracle(cfg, steps, two):
     s.step(steps)
     o.step(steps)
     (_compare2 if two else _compare)(s, o, "large tiles %s nx=%d" % ("2D" if two else "1D", cfg["nx"]))
+
+
+@pytest.mark.parametrize("cfg,steps,two", [
+    (_fourier(nx=64, qx_half=5, kn=0.05, eta0=0.2, collision=I.SHAKHOV_DENSE, chi_mode=1), 15, False),
+    (dict(I.BASE, flow=I.COUETTE, nx=48, qx_half=4, qy=4, kn=0.06, eta0=0.2, uy_left=-0.3, uy_right=0.3,
+          collision=I.SHAKHOV_DENSE, chi_mode=1), 10, True),
+    (dict(I.BASE, flow=I.POISEUILLE, nx=40, qx_half=4, qy=3, kn=0.08, eta0=0.15, ay=0.05, grid=I.GRID_TANH,
+          stretch=1.5, chi_mode=1), 12, True),
+])
+def test_reduced_models_with_revised_enskog_chi_match_oracle(cfg, steps, two):
+    """chi_mode 1: chi at the revised Enskog average density of the stage
+    input, computed by its own pass over the phi rows before each stage."""
+    s, o = (_pair2 if two else _pair)(cfg, 180 + cfg["nx"])
+    s.step(steps)
+    o.step(steps)
+    (_compare2 if two else _compare)(s, o, "chi_mode 1 %s nx=%d" % ("2D" if two else "1D", cfg["nx"]))

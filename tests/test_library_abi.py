@@ -126,7 +126,8 @@ def test_reduced_model_validation():
     from paper_2308_15407_amd import fdlb as F
     ok = dict(I.BASE, nx=32, qx_half=8)
     assert F.fdlb_r1_workspace_bytes([ok, dict(ok, qx_half=32)]) > 0
-    for bad in (dict(ok, uy_left=0.1), dict(ok, ay=1e-3), dict(ok, chi_mode=1), dict(ok, precision=1),
+    assert F.fdlb_r1_workspace_bytes([dict(ok, chi_mode=1)]) > 0
+    for bad in (dict(ok, uy_left=0.1), dict(ok, ay=1e-3), dict(ok, chi_mode=1, nx=4096), dict(ok, precision=1),
                 dict(ok, qx_half=33), dict(ok, nx=5)):
         with pytest.raises(F.FdlbError):
             F.fdlb_r1_workspace_bytes([bad])
