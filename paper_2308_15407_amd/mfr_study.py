@@ -19,6 +19,7 @@ by less than RTOL (relative) over the last chunk of steps.
 
     python -m paper_2308_15407_amd.mfr_study run [--out PATH]
     python -m paper_2308_15407_amd.mfr_study qscan [--out PATH]
+    python -m paper_2308_15407_amd.mfr_study reduced [--out PATH]
 
 run writes {"R": {...: {"kn": [...], "eta0": [...], "mfr": [...], "steps": [...]}}};
 qscan (the dependence on the half-range order, the figure's panel (b)) writes
@@ -37,6 +38,7 @@ import fdlb_inputs as I
 HERE = os.path.dirname(os.path.abspath(__file__))
 DEFAULT_OUT = os.path.join(HERE, "mfr_results.json")
 DEFAULT_QSCAN_OUT = os.path.join(HERE, "mfr_qscan_results.json")
+DEFAULT_REDUCED_OUT = os.path.join(HERE, "mfr_reduced_results.json")
 
 R_VALUES = (2.0, 5.0, 10.0, 20.0)
 KN_VALUES = tuple(float(v) for v in np.round(np.logspace(-2, math.log10(2.0), 12), 5))
@@ -87,13 +89,14 @@ def mfr(solver, i):
 RTOL = 1e-7
 
 
-def settle(cfgs, tol=1e-10, max_steps=600000, chunk=25000, log=print):
+def settle(cfgs, tol=1e-10, max_steps=600000, chunk=25000, log=print, reduced=False):
     """Step one batch until every case is steady (residual below tol, or flow
     rate changed by at most RTOL over a chunk) or max_steps; returns the flow
     rates, the steps at which each case settled (0 if never), the settled
-    mask, the residuals and the wall time."""
-    from .solver import Solver
-    s = Solver(cfgs, graph_steps=100)
+    mask, the residuals and the wall time.  reduced=True runs the batch in the
+    paper's reduced 2D form (no residual: the flow-rate criterion alone)."""
+    from .solver import ReducedSolver, Solver
+    s = ReducedSolver(cfgs) if reduced else Solver(cfgs, graph_steps=100)
     t0 = time.perf_counter()
     nc = len(cfgs)
     prev = np.full(nc, np.nan)
@@ -105,7 +108,7 @@ def settle(cfgs, tol=1e-10, max_steps=600000, chunk=25000, log=print):
     while k < max_steps and not np.all(done):
         s.step(chunk)
         k += chunk
-        r = s.residual()
+        r = np.full(nc, np.inf) if reduced else s.residual()
         m_new = np.array([mfr(s, i) for i in range(nc)])
         newly = ~done & np.isfinite(m_new) & ((r < tol) | (np.abs(m_new - prev) <= RTOL * np.abs(m_new)))
         done |= newly | ~np.isfinite(m_new)
@@ -119,18 +122,20 @@ def settle(cfgs, tol=1e-10, max_steps=600000, chunk=25000, log=print):
     return m, steps, done, res, wall
 
 
-def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print):
+def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print, reduced=False):
+    """reduced=True: the cases with Kn < 0.5 (Q_x^h = 16; 4 x 16 x 4 = 256 rows
+    fit the reduced kernel) in the paper's reduced 2D form."""
     specs, cfgs = [], []
     for R in R_VALUES:
         for kn in KN_VALUES:
             c = case(R, kn)
-            if c is not None:
+            if c is not None and not (reduced and c["qx_half"] > 16):
                 specs.append((R, kn, c["eta0"]))
                 cfgs.append(c)
     log("%d cases" % len(cfgs))
-    m, steps, done, res, wall = settle(cfgs, tol, max_steps, chunk, log)
+    m, steps, done, res, wall = settle(cfgs, tol, max_steps, chunk, log, reduced=reduced)
     result = {"tol": tol, "rtol_mfr": RTOL, "chunk": chunk, "ay": AY, "eta_max": ETA_MAX,
-              "wall_s": round(wall, 2), "R": {}}
+              "wall_s": round(wall, 2), "form": "reduced 2D" if reduced else "3D lattice", "R": {}}
     for i, (R, kn, eta0) in enumerate(specs):
         d = result["R"].setdefault("%g" % R, {"kn": [], "eta0": [], "mfr": [], "steps": [], "resid": []})
         d["kn"].append(kn); d["eta0"].append(round(eta0, 6)); d["mfr"].append(float(m[i]))
@@ -174,7 +179,7 @@ def run_qscan(out=DEFAULT_QSCAN_OUT, tol=1e-10, max_steps=600000, chunk=25000, l
 
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["run", "qscan"])
+    ap.add_argument("cmd", choices=["run", "qscan", "reduced"])
     ap.add_argument("--out", default=None)
     ap.add_argument("--tol", type=float, default=1e-10)
     ap.add_argument("--max-steps", type=int, default=600000)
@@ -182,6 +187,8 @@ def main():
     log = lambda msg: print(msg, flush=True)
     if a.cmd == "run":
         run(a.out or DEFAULT_OUT, a.tol, a.max_steps, log=log)
+    elif a.cmd == "reduced":
+        run(a.out or DEFAULT_REDUCED_OUT, a.tol, a.max_steps, log=log, reduced=True)
     else:
         run_qscan(a.out or DEFAULT_QSCAN_OUT, a.tol, a.max_steps, log=log)
 

@@ -165,3 +165,7 @@ class ReducedSolver:
 
     def dt(self, c=0):
         return F.fdlb_r1_dt(self.handle, c)
+
+    def grid(self, c=0):
+        """Cell centres and metric dx/deta of case c."""
+        return F.fdlb_case_grid(self.cases[c])

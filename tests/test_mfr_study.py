@@ -95,3 +95,27 @@ def test_committed_order_scan_converges_in_q():
     last = [res["Q"][q]["mfr"][-1] for q in qs]
     assert abs(last[-1] - last[-2]) < 1e-3 * last[-1]
     assert abs(last[0] - last[-1]) > 10 * abs(last[-2] - last[-1])
+
+
+def test_reduced_form_flow_rates_agree_with_the_lattice():
+    """The same cases (Kn < 0.5, Q_x^h = 16) solved in the paper's reduced 2D
+    form and on the 3D lattice: two discretisations of one model that differ
+    only through the nonlinear WENO weights.  Settled flow rates agree to 3e-4
+    below eta0 = 0.1 and to 5e-3 in the dense cases, where the layered density
+    makes the weights matter most."""
+    import os
+    if not (os.path.exists(M.DEFAULT_REDUCED_OUT) and os.path.exists(M.DEFAULT_OUT)):
+        pytest.skip("no committed results")
+    red = json.load(open(M.DEFAULT_REDUCED_OUT))
+    lat = json.load(open(M.DEFAULT_OUT))
+    n = 0
+    for R, d in red["R"].items():
+        d3 = lat["R"][R]
+        for kn, eta0, m, st in zip(d["kn"], d["eta0"], d["mfr"], d["steps"]):
+            i = d3["kn"].index(kn)
+            if st <= 0 or d3["steps"][i] <= 0:
+                continue
+            rel = abs(m - d3["mfr"][i]) / d3["mfr"][i]
+            assert rel < (3e-4 if eta0 < 0.1 else 5e-3), (R, kn, eta0, rel)
+            n += 1
+    assert n >= 20
