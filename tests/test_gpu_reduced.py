@@ -175,3 +175,24 @@ def test_reduced_models_with_revised_enskog_chi_match_oracle(cfg, steps, two):
     s.step(steps)
     o.step(steps)
     (_compare2 if two else _compare)(s, o, "chi_mode 1 %s nx=%d" % ("2D" if two else "1D", cfg["nx"]))
+
+
+@pytest.mark.parametrize("eta0,dT", [(0.01, 0.5), (0.1, 0.1), (0.2, 0.5)])
+def test_reduced_1d_steady_state_agrees_with_the_lattice(eta0, dT):
+    """The same Fourier case near its steady state on the 3D lattice (Q_y = Q_z
+    = 4) and in the reduced 1D form: two discretisations of one model that
+    differ only through the nonlinear WENO weights, so T and the heat flux
+    agree to a small fraction of their variation across the channel."""
+    from paper_2308_15407_amd.solver import ReducedSolver, Solver
+    R = 10.0
+    chi = 0.5 * (2 - eta0) / (1 - eta0) ** 3
+    cfg = _fourier(nx=64, qx_half=8, qy=4, qz=4, kn=1.0 / (6 * np.sqrt(2) * eta0 * chi * R), eta0=eta0,
+                   t_left=1.0 - dT, t_right=1.0 + dT, collision=I.SHAKHOV_DENSE)
+    s3, s1 = Solver(cfg, graph_steps=100), ReducedSolver(cfg)
+    s3.step(12000)
+    s1.step(12000)
+    m3, m1 = s3.moments(0), s1.moments(0)
+    dTr = np.max(np.abs(m3[3] - m1[3])) / (np.max(m3[3]) - np.min(m3[3]))
+    dq = np.max(np.abs(m3[4] - m1[4])) / np.max(np.abs(m3[4]))
+    print("eta0 %.2f dT %.1f: T %.1e of its range, q_x %.1e of its size" % (eta0, dT, dTr, dq), flush=True)
+    assert dTr < 5e-3 and dq < 5e-3, (dTr, dq)
