@@ -90,8 +90,10 @@ def measure(cfg, steps, warmup, retune, graph_steps=50):
 
 
 def roofline(prof, nodes, prec, kernel_name, workload):
-    """Dominant kernel: the stage-2 update (reads f^(1) and f^n, writes f^(2)):
-    3 passes x bytes per population x nodes, algorithmic."""
+    """The kernel whose bytes scale with the nodes: the stage-2 update (reads
+    f^(1) and f^n, writes f^(2)): 3 passes x bytes per population x nodes,
+    algorithmic.  (At small sizes the per-cell table pass can take as long,
+    as a latency chain of little traffic.)"""
     s_bytes = 8 if prec == 0 else 4
     t_ms = prof[2] if prec == 0 else prof[5]
     alg = 3.0 * s_bytes * nodes
