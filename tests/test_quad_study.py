@@ -75,3 +75,21 @@ def test_committed_results_are_consistent():
                 assert e["q_min_bound"] == Q.q_min(e["q"], bound)
                 # the error falls by an order of magnitude or more over the scanned orders
                 assert e["eps"][-1] < 0.1 * e["eps"][0], (flow, R, eta0)
+
+
+def test_finer_grid_keeps_the_dense_orders_and_raises_the_rarefied_ones():
+    """Poiseuille at 20 cells per sigma against 10: the dense orders stay, the
+    rarefied ones grow by at most a few (toward the paper's grid of 100)."""
+    fine_path = os.path.join(Q.HERE, "quad_results_poiseuille_cps20.json")
+    if not (os.path.exists(fine_path) and os.path.exists(Q.DEFAULT_OUT)):
+        pytest.skip("no committed results")
+    fine = json.load(open(fine_path))["flows"]["poiseuille"]["R"]
+    base = json.load(open(Q.DEFAULT_OUT))["flows"]["poiseuille"]["R"]
+    for R, by_eta in fine.items():
+        for eta0, e in by_eta.items():
+            b = base[R][eta0]
+            assert e["q_min"] == Q.q_min(e["q"], e["eps"])
+            if float(eta0) >= 0.1:
+                assert e["q_min"] == b["q_min"], (R, eta0)
+            else:
+                assert b["q_min"] <= e["q_min"] <= b["q_min"] + 4, (R, eta0, b["q_min"], e["q_min"])
