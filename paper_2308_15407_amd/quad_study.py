@@ -19,8 +19,9 @@ dense Prandtl number, the local contact value chi(eta0 n).  Q_y = 5 on the
 flows with a y-velocity (the order the paper imposes there), Q_y = 4 for the
 Fourier flow, Q_z = 4 (the product lattice needs it for the cubic terms).
 The grid is uniform with CELLS_PER_SIGMA cells per molecular diameter (the
-paper uses 100; the order needed is a property of velocity space, and a
-coarser grid keeps the Q = 200 reference runs affordable).
+paper uses 100; a coarser grid keeps the Q = 200 reference runs affordable,
+and resolves the Knudsen layers of rarefied cases less finely, so that the
+orders found there are lower bounds).
 
     python -m paper_2308_15407_amd.quad_study run [--out PATH] [--cells-per-sigma N]
 
