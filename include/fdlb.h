@@ -230,7 +230,7 @@ void fdlb_destroy(fdlb_handle h);
      ignored.  Rows: [0, 2 qx_half) phi, then theta.
    - Couette and Poiseuille (flows 1, 2), 2D: phi = int f dp_z and theta =
      int p_z^2 f dp_z on the 2 qx_half x qy (x, y) nodes (eq:evolution_2D with
-     the body force, moments eq:macro2D), 4 qx_half qy <= 256.  Rows: phi
+     the body force, moments eq:macro2D), 4 qx_half qy <= 640.  Rows: phi
      (kx, ky) at kx qy + ky, then theta in the same order.
    Every case: precision FDLB_F64, qx_half <= 32; chi_mode 0 or 1 (the
    revised Enskog average, by its own pass over the phi rows before each

@@ -102,7 +102,9 @@ struct CaseDev {
 // [R][nx] arrays: phi (kx, ky) at kx qy + ky, then theta; R = 4 qh qy.
 constexpr int R1_TILE = 32;    // cells per block of the reduced stage kernel (up to 128 rows)
 constexpr int R1_TILE_2 = 16;  // cells per block for 129..256 rows
-constexpr int R1_RMAX = 256;   // rows of a reduced case
+constexpr int R1_RMAX = 256;
+constexpr int R1_TILE_BIG = 4; // cells per block for 257..R1_RMAX_BIG rows (2D, qx_half qy <= 160)
+constexpr int R1_RMAX_BIG = 640;   // rows of a reduced case
 constexpr int R1_HALO = 6;     // moment halo (the one-sided wall stencils reach 6 cells)
 struct R1Dev {
   int nx, qh, qy, R;

@@ -1340,7 +1340,7 @@ __global__ void __launch_bounds__(512) k_r1_nbar(const R1Dev *__restrict__ cases
 // pass, the body force on the y-nodes (2D), relaxation and the TVD-RK3
 // combination (eq:rk3).  D is the dimension of the reduced model, RM the
 // largest row count of the launch (it sizes the LDS) and TS the cells per
-// block (32 up to 128 rows, 16 above, 8 on small maps).
+// block (32 up to 128 rows, 16 up to 256, 4 above; 8 on small maps).
 template <int STAGE, int RM, int D, int TS>
 __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
   constexpr int W = TS + 2 * R1_HALO, QYM = D == 2 ? MAXQY : 1;
@@ -1687,6 +1687,7 @@ static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, const int2 
 // cells per block: 32 up to 128 rows, 16 above; maps that would have at most
 // SMALL_TABLE_MAP blocks take CTILE_SMALL cells per block (latency-bound sizes)
 int r1_tile(int rmax, int total_cells) {
+  if (rmax > R1_RMAX) return R1_TILE_BIG;
   const int t = rmax <= 128 ? R1_TILE : R1_TILE_2;
   return (total_cells + t - 1) / t <= SMALL_TABLE_MAP ? CTILE_SMALL : t;
 }
@@ -1694,10 +1695,16 @@ int r1_tile(int rmax, int total_cells) {
 template <int RM, int D>
 static hipError_t r1_by_tile(const R1Dev *cases, const int2 *m, int nblocks, int tile, const int2 *mn, int nn,
                              size_t ldsn, long nsteps, hipStream_t s) {
-  constexpr int TL = RM <= 128 ? R1_TILE : R1_TILE_2;
-  if (tile == TL) r1_steps<RM, D, TL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
-  else if (tile == CTILE_SMALL) r1_steps<RM, D, CTILE_SMALL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
-  else return hipErrorInvalidValue;
+  if constexpr (RM > R1_RMAX) {
+    // the largest row counts take 4-cell tiles only (the LDS holds RM rows)
+    if (tile != R1_TILE_BIG) return hipErrorInvalidValue;
+    r1_steps<RM, D, R1_TILE_BIG>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
+  } else {
+    constexpr int TL = RM <= 128 ? R1_TILE : R1_TILE_2;
+    if (tile == TL) r1_steps<RM, D, TL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
+    else if (tile == CTILE_SMALL) r1_steps<RM, D, CTILE_SMALL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
+    else return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 
@@ -1712,6 +1719,8 @@ hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int r
   } else if (dim == 2) {
     if (rmax <= 128) return r1_by_tile<128, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
     if (rmax <= R1_RMAX) return r1_by_tile<R1_RMAX, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
+    if (rmax <= R1_RMAX_BIG)
+      return r1_by_tile<R1_RMAX_BIG, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
   }
   return hipErrorInvalidValue;
 }

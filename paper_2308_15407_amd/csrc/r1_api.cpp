@@ -53,7 +53,10 @@ static int r1_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     why = "reduced 1D model (Fourier flow): no y-motion (walls, initial state) and no body force";
     return -1;
   }
-  if (dim == 2 && 4 * p.qx_half * p.qy > R1_RMAX) { why = "reduced 2D model: 4 qx_half qy must be <= 256"; return -1; }
+  if (dim == 2 && 4 * p.qx_half * p.qy > R1_RMAX_BIG) {
+    why = "reduced 2D model: 4 qx_half qy must be <= 640";
+    return -1;
+  }
   if (p.precision != FDLB_F64) { why = "reduced model: FP64 storage only"; return -1; }
   fdlb_params q = p;
   if (dim == 1) q.qy = 2;
@@ -121,7 +124,7 @@ extern "C" size_t fdlb_r1_workspace_bytes(const fdlb_params *cases, int ncases) 
       return 0;
     }
     total += r1_case_bytes(c);
-    tiles += r1_tiles(c, CTILE_SMALL);   // the smallest tile bounds the map
+    tiles += r1_tiles(c, R1_TILE_BIG);   // the smallest tile bounds the map
     if (c.p.chi_mode == 1) tiles += r1_tiles(c, NBAR_TILE);
   }
   return total + al256(sizeof(int) * 2 * tiles) + 256;   // two map regions, each 256-byte aligned

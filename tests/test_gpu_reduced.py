@@ -117,6 +117,12 @@ def _compare2(s, o, label, tol=TOL64):
           t_left=0.9, t_right=1.1, collision=I.SHAKHOV_FIXED, pr_fixed=0.6, j1_shear=0), 10),
     # free molecular with force, last tile of 2 cells at 32-cell tiles
     (dict(I.BASE, flow=I.POISEUILLE, nx=34, qx_half=4, qy=3, kn=0.0, eta0=0.0, ay=0.1), 20),
+    # above 256 rows (4-cell tiles): 320 rows, last tile of 1 cell
+    (dict(I.BASE, flow=I.COUETTE, nx=37, qx_half=16, qy=5, kn=0.1, eta0=0.1, uy_left=-0.4, uy_right=0.4,
+          collision=I.SHAKHOV_DENSE, j1_shear=1), 6),
+    # 580 rows: the Poiseuille order of the quadrature test (Q_x^h = 29, Q_y = 5), tanh grid
+    (dict(I.BASE, flow=I.POISEUILLE, nx=30, qx_half=29, qy=5, kn=0.05, eta0=0.2, ay=0.05, grid=I.GRID_TANH,
+          stretch=1.3, collision=I.SHAKHOV_DENSE), 5),
 ])
 def test_reduced_2d_model_matches_oracle(cfg, steps):
     s, o = _pair2(cfg, 120 + cfg["nx"])

@@ -131,9 +131,10 @@ def test_reduced_model_validation():
                 dict(ok, qx_half=33), dict(ok, nx=5)):
         with pytest.raises(F.FdlbError):
             F.fdlb_r1_workspace_bytes([bad])
-    # 2D (Couette, Poiseuille): 4 qx_half qy <= 256, one dimension per batch
+    # 2D (Couette, Poiseuille): 4 qx_half qy <= 640, one dimension per batch
     ok2 = dict(I.BASE, flow=I.POISEUILLE, nx=32, qx_half=8, qy=5, ay=1e-3)
     assert F.fdlb_r1_workspace_bytes([ok2, dict(ok2, flow=I.COUETTE, uy_left=0.2, qx_half=16, qy=4)]) > 0
-    for bad in ([dict(ok2, qx_half=16, qy=5)], [ok, ok2]):
+    assert F.fdlb_r1_workspace_bytes([ok2, dict(ok2, qx_half=29), dict(ok2, qx_half=32)]) > 0
+    for bad in ([dict(ok2, qx_half=32, qy=6)], [ok, ok2]):
         with pytest.raises(F.FdlbError):
             F.fdlb_r1_workspace_bytes(bad)
