@@ -1356,6 +1356,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   __shared__ double s_nw[2];
   __shared__ double s_lam[D == 2 ? MAXQH : RM / 4][NB + 1];   // Lagrange rows (padded: bank spread)
   __shared__ double s_bh[2][NB];            // base nodes P_m and h_Q(P_m)
+  __shared__ double s_px[2 * MAXQH], s_py[QYM], s_km[QYM * QYM];   // x-nodes, y-nodes, force matrix
   const int nx = c.nx, qh = c.qh, qy = c.qy, Q2 = 2 * qh, Kh = Q2 * qy, R = c.R;
   const int c0 = bm.y * TS, own = min(TS, nx - c0);
   const int tid = threadIdx.x;
@@ -1371,6 +1372,9 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   }
   for (int it = tid; it < qh * NB; it += blockDim.x) s_lam[it / NB][it % NB] = lat[lo.lam + it];
   for (int it = tid; it < NB; it += blockDim.x) { s_bh[0][it] = lat[lo.bP + it]; s_bh[1][it] = lat[lo.hQ + it]; }
+  if (tid < Q2) s_px[tid] = lat[lo.px + tid];
+  if (D == 2 && tid < qy) s_py[tid] = lat[lo.py + tid];
+  if (D == 2 && tid < qy * qy) s_km[tid] = lat[lo.kmat + tid];
   __syncthreads();
 
   // moments of the staged cells (8 lanes per cell, each summing every 8th
@@ -1384,8 +1388,8 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     if (live)
       for (int r = sub; r < Kh; r += 8) {
         const double v = s_g[r][wc];
-        n += v; jx += lat[lo.px + r / qy] * v;
-        if (D == 2) jy += lat[lo.py + r % qy] * v;
+        n += v; jx += s_px[r / qy] * v;
+        if (D == 2) jy += s_py[r % qy] * v;
       }
 #pragma unroll
     for (int off = 1; off < 8; off <<= 1) {
@@ -1395,7 +1399,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     double pin = 0.0, th = 0.0, qx = 0.0, qy_ = 0.0;   // pin: sum of |xi_in-plane|^2 phi
     if (live)
       for (int r = sub; r < Kh; r += 8) {
-        const double cx = lat[lo.px + r / qy] - ux, cy = D == 2 ? lat[lo.py + r % qy] - uy : 0.0;
+        const double cx = s_px[r / qy] - ux, cy = D == 2 ? s_py[r % qy] - uy : 0.0;
         const double ph = s_g[r][wc], tt = s_g[Kh + r][wc], c2 = cx * cx + cy * cy;
         pin += c2 * ph; th += tt;
         qx += cx * (0.5 * c2 * ph + 0.5 * tt);
@@ -1413,25 +1417,29 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       const double nc = c.chi_mode == 1 ? c.nbar[cell] : n;
       s_l[0][wc] = log(n); s_l[1][wc] = log(chi_cs(c.eta0 * nc)); s_l[2][wc] = log(T_);
     }
-  } else if (tid == 448 || tid == 480) {
+  } else if (tid >= 448) {
     // impenetrability: the incoming phi rows reach the wall face through the
     // fully interior candidate; n_w makes the net mass flux vanish.  Every
     // tile whose stencils reach a wall's ghosts (cells within 3 of it) takes
-    // that wall's density; the cells it needs are staged.
-    const int wall = tid == 448 ? 0 : 1;
-    const bool here = wall == 0 ? c0 < 3 : c0 + own + 2 >= nx;
+    // that wall's density; the cells it needs are staged.  The last wave
+    // sums it: lanes 0-31 the left wall, 32-63 the right, each over every
+    // 32nd phi row, then a butterfly within the half.
+    const int wall = (tid - 448) >> 5, ln = tid & 31;
+    const bool here = wall == 0 ? c0 < 3 : c0 + own + 2 >= nx;   // uniform over the half
+    double in = 0.0;
     if (here) {
-      double in = 0.0;
       const int w0 = wall == 0 ? R1_HALO : nx - 1 - c0 + R1_HALO;   // the wall cell
       const int st = wall == 0 ? 1 : -1;                             // into the domain
-      for (int r = 0; r < Kh; r++) {
-        const double p = lat[lo.px + r / qy];
+      for (int r = ln; r < Kh; r += 32) {
+        const double p = s_px[r / qy];
         if ((wall == 0) != (p < 0.0)) continue;
         const double v0 = s_g[r][w0 + 2 * st], v1 = s_g[r][w0 + st], v2 = s_g[r][w0];
         in += p * (v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0));
       }
-      s_nw[wall] = -in / c.wallD[wall];
     }
+#pragma unroll
+    for (int off = 1; off < 32; off <<= 1) in += __shfl_xor(in, off, 64);
+    if (here && ln == 0) s_nw[wall] = -in / c.wallD[wall];
   }
   __syncthreads();
 
@@ -1553,7 +1561,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       const int k = k0 + j;
       if (k >= qh) break;
       const double x0 = j == 0 ? x0a : x0b;
-      const double dk = lat[lo.px + k] - u, ck = lat[lo.ck + k];
+      const double dk = s_px[k] - u, ck = lat[lo.ck + k];
       const double X[4] = {x0, sg * (dk * x0 + ck * mb0), dk * dk * x0 + ck * (dk * mb0 + mb1),
                            sg * (dk * dk * dk * x0 + ck * (dk * dk * mb0 + dk * mb1 + mb2))};
       const int kx = h * qh + k;
@@ -1576,7 +1584,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     if (cl0 >= own) continue;
     const int ncl = min(SW, own - cl0);
     const int rh = r % Kh, ky = rh % qy;
-    const double p = lat[lo.px + rh / qy];
+    const double p = s_px[rh / qy];
     const double *row = s_g[r];
     const double fwl = nwl * c.gw[r], fwr = nwr * c.gw[R + r];
     // face j (left face of cell j) in the upwind frame, with the wall rules:
@@ -1625,7 +1633,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       if (D == 2 && c.ay != 0.0) {
         // -a_y d/dp_y on the y-nodes of this x-node and population (App. A kernel)
         double sF = 0.0;
-        for (int k2 = 0; k2 < qy; k2++) sF += lat[lo.kmat + ky * qy + k2] * s_g[r - ky + k2][cl + R1_HALO];
+        for (int k2 = 0; k2 < qy; k2++) sF += s_km[ky * qy + k2] * s_g[r - ky + k2][cl + R1_HALO];
         L -= c.ay * sF;
       }
       const double adv = cen + c.dt * L;
