@@ -123,13 +123,13 @@ def settle(cfgs, tol=1e-10, max_steps=600000, chunk=25000, log=print, reduced=Fa
 
 
 def run(out=DEFAULT_OUT, tol=1e-10, max_steps=600000, chunk=25000, log=print, reduced=False):
-    """reduced=True: the cases with Kn < 0.5 (Q_x^h = 16; 4 x 16 x 4 = 256 rows
-    fit the reduced kernel) in the paper's reduced 2D form."""
+    """reduced=True: every case in the paper's reduced 2D form (Q_x^h = 16 or
+    32 with Q_y = 4: up to 4 x 32 x 4 = 512 rows)."""
     specs, cfgs = [], []
     for R in R_VALUES:
         for kn in KN_VALUES:
             c = case(R, kn)
-            if c is not None and not (reduced and c["qx_half"] > 16):
+            if c is not None:
                 specs.append((R, kn, c["eta0"]))
                 cfgs.append(c)
     log("%d cases" % len(cfgs))

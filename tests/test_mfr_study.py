@@ -98,11 +98,12 @@ def test_committed_order_scan_converges_in_q():
 
 
 def test_reduced_form_flow_rates_agree_with_the_lattice():
-    """The same cases (Kn < 0.5, Q_x^h = 16) solved in the paper's reduced 2D
-    form and on the 3D lattice: two discretisations of one model that differ
-    only through the nonlinear WENO weights.  Settled flow rates agree to 3e-4
-    below eta0 = 0.1 and to 5e-3 in the dense cases, where the layered density
-    makes the weights matter most."""
+    """The same cases (Q_x^h = 16 below Kn = 0.5, 32 above) solved in the
+    paper's reduced 2D form and on the 3D lattice: two discretisations of one
+    model that differ only through the nonlinear WENO weights.  Settled flow
+    rates agree to 1e-5 in the rarefied cases, to 3e-4 below eta0 = 0.1 and to
+    5e-3 in the dense cases, where the layered density makes the weights
+    matter most."""
     import os
     if not (os.path.exists(M.DEFAULT_REDUCED_OUT) and os.path.exists(M.DEFAULT_OUT)):
         pytest.skip("no committed results")
@@ -116,6 +117,6 @@ def test_reduced_form_flow_rates_agree_with_the_lattice():
             if st <= 0 or d3["steps"][i] <= 0:
                 continue
             rel = abs(m - d3["mfr"][i]) / d3["mfr"][i]
-            assert rel < (3e-4 if eta0 < 0.1 else 5e-3), (R, kn, eta0, rel)
+            assert rel < (1e-5 if kn >= 0.5 else 3e-4 if eta0 < 0.1 else 5e-3), (R, kn, eta0, rel)
             n += 1
-    assert n >= 20
+    assert n >= 32
