@@ -1357,7 +1357,11 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   __shared__ double s_lam[D == 2 ? MAXQH : RM / 4][NB + 1];   // Lagrange rows (padded: bank spread)
   __shared__ double s_bh[2][NB];            // base nodes P_m and h_Q(P_m)
   __shared__ double s_px[2 * MAXQH], s_py[QYM], s_km[QYM * QYM];   // x-nodes, y-nodes, force matrix
-  const int nx = c.nx, qh = c.qh, qy = c.qy, Q2 = 2 * qh, Kh = Q2 * qy, R = c.R;
+  __shared__ unsigned char s_rk[D == 2 ? RM / 2 : 1][2];             // 2D: phi row -> (kx, ky)
+  const int nx = c.nx, qh = c.qh, qy = D == 1 ? 1 : c.qy, Q2 = 2 * qh, Kh = Q2 * qy, R = c.R;
+  // node indices of a phi row without a division in the row loops
+  auto kx_of = [&](int r) -> int { return D == 2 ? s_rk[r][0] : r; };
+  auto ky_of = [&](int r) -> int { return D == 2 ? s_rk[r][1] : 0; };
   const int c0 = bm.y * TS, own = min(TS, nx - c0);
   const int tid = threadIdx.x;
   const double *lat = c.lat;
@@ -1375,6 +1379,11 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
   if (tid < Q2) s_px[tid] = lat[lo.px + tid];
   if (D == 2 && tid < qy) s_py[tid] = lat[lo.py + tid];
   if (D == 2 && tid < qy * qy) s_km[tid] = lat[lo.kmat + tid];
+  if (D == 2)
+    for (int it = tid; it < Kh; it += blockDim.x) {
+      const int kx = it / qy;
+      s_rk[it][0] = (unsigned char)kx; s_rk[it][1] = (unsigned char)(it - kx * qy);
+    }
   __syncthreads();
 
   // moments of the staged cells (8 lanes per cell, each summing every 8th
@@ -1388,8 +1397,8 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     if (live)
       for (int r = sub; r < Kh; r += 8) {
         const double v = s_g[r][wc];
-        n += v; jx += s_px[r / qy] * v;
-        if (D == 2) jy += s_py[r % qy] * v;
+        n += v; jx += s_px[kx_of(r)] * v;
+        if (D == 2) jy += s_py[ky_of(r)] * v;
       }
 #pragma unroll
     for (int off = 1; off < 8; off <<= 1) {
@@ -1399,7 +1408,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     double pin = 0.0, th = 0.0, qx = 0.0, qy_ = 0.0;   // pin: sum of |xi_in-plane|^2 phi
     if (live)
       for (int r = sub; r < Kh; r += 8) {
-        const double cx = s_px[r / qy] - ux, cy = D == 2 ? s_py[r % qy] - uy : 0.0;
+        const double cx = s_px[kx_of(r)] - ux, cy = D == 2 ? s_py[ky_of(r)] - uy : 0.0;
         const double ph = s_g[r][wc], tt = s_g[Kh + r][wc], c2 = cx * cx + cy * cy;
         pin += c2 * ph; th += tt;
         qx += cx * (0.5 * c2 * ph + 0.5 * tt);
@@ -1431,7 +1440,7 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
       const int w0 = wall == 0 ? R1_HALO : nx - 1 - c0 + R1_HALO;   // the wall cell
       const int st = wall == 0 ? 1 : -1;                             // into the domain
       for (int r = ln; r < Kh; r += 32) {
-        const double p = s_px[r / qy];
+        const double p = s_px[kx_of(r)];
         if ((wall == 0) != (p < 0.0)) continue;
         const double v0 = s_g[r][w0 + 2 * st], v1 = s_g[r][w0 + st], v2 = s_g[r][w0];
         in += p * (v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0));
@@ -1583,8 +1592,8 @@ __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ case
     const int r = it / NS, q = it - r * NS, cl0 = q * SW;
     if (cl0 >= own) continue;
     const int ncl = min(SW, own - cl0);
-    const int rh = r % Kh, ky = rh % qy;
-    const double p = s_px[rh / qy];
+    const int rh = r < Kh ? r : r - Kh, ky = ky_of(rh);
+    const double p = s_px[kx_of(rh)];
     const double *row = s_g[r];
     const double fwl = nwl * c.gw[r], fwr = nwr * c.gw[R + r];
     // face j (left face of cell j) in the upwind frame, with the wall rules:
