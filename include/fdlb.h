@@ -234,10 +234,10 @@ void fdlb_destroy(fdlb_handle h);
      (kx, ky) at kx qy + ky, then theta in the same order.
    Every case: precision FDLB_F64, qx_half <= 32; chi_mode 0 or 1 (the
    revised Enskog average, by its own pass over the phi rows before each
-   stage; nx <= 4000); qz is ignored; one dimension per batch.  A batch
-   launches with the tile of its largest row count: 32 cells up to 128 rows,
-   16 up to 256, 4 above, so mixing 2D cases above and below 256 rows slows
-   the smaller ones.  State layout: [rows][nx] doubles, x-nodes in
+   stage; nx <= 4000); qz is ignored; one dimension per batch.  Cases of at
+   most 256 rows and those above launch as two groups, one after the other
+   in each stage, each with the tile of its largest row count (32 cells up
+   to 128 rows, 16 up to 256, 4 above); results do not depend on the tile.  State layout: [rows][nx] doubles, x-nodes in
    the order of fdlb_case_lattice's, cells contiguous.  Each TVD-RK3 step is
    three launches of one fused kernel; the calls follow the 3D solver's
    conventions (caller-owned workspace, stream, error codes). */

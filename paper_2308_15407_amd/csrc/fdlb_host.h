@@ -45,15 +45,20 @@ enum {
 
 // kernel launchers (fdlb_kernels.hip); map arrays are int4 {case, tile, chunk, 0}
 // e0/e1 (optional): events recorded at the kernel's own start and end (timing)
-// reduced models: nsteps TVD-RK3 steps of every case (map: int2 {case, tile}
-// per block of `tile` = r1_tile(rmax, total cells) cells; rmax: the largest
-// row count of the cases; dim: 1 or 2, the same for every case), and the
-// moments of case c into its mom array
+// reduced models: nsteps TVD-RK3 steps of every case, launched per group of
+// cases (at most 256 rows, more than 256), each with its own map (int2
+// {case, tile} per block of `tile` = r1_tile(rmax, group cells) cells) and
+// rmax, the largest row count of its cases; dim: 1 or 2, the same for every
+// case; and the moments of case c into its mom array
+struct R1Group {
+  const int *map;
+  int nblocks, rmax, tile;
+};
 int r1_tile(int rmax, int total_cells);
 // (map_n: int2 {case, tile} per NBAR_TILE cells of the chi_mode 1 cases, with
 // lds_n the bytes of the largest window of a tile; nblocks_n = 0 if none)
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile,
-                          const int *map_n, int nblocks_n, size_t lds_n, long nsteps, hipStream_t s);
+hipError_t launch_r1_step(const R1Dev *cases, const R1Group *groups, int ngroups, int dim, const int *map_n,
+                          int nblocks_n, size_t lds_n, long nsteps, hipStream_t s);
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s);
 // wide: the map may hold cases with qx_half > MAXQH (adds the wide pass);
 // tile: the cells per block the map was built with (CTILE or CTILE_SMALL)

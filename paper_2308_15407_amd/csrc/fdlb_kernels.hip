@@ -1340,7 +1340,8 @@ __global__ void __launch_bounds__(512) k_r1_nbar(const R1Dev *__restrict__ cases
 // pass, the body force on the y-nodes (2D), relaxation and the TVD-RK3
 // combination (eq:rk3).  D is the dimension of the reduced model, RM the
 // largest row count of the launch (it sizes the LDS) and TS the cells per
-// block (32 up to 128 rows, 16 up to 256, 4 above; 8 on small maps).
+// block (32 up to 128 rows, 16 up to 256, 4 above; 8 on small maps of at most
+// 256 rows).
 template <int STAGE, int RM, int D, int TS>
 __global__ void __launch_bounds__(512) k_r1_stage(const R1Dev *__restrict__ cases, const int2 *__restrict__ map) {
   constexpr int W = TS + 2 * R1_HALO, QYM = D == 2 ? MAXQY : 1;
@@ -1689,20 +1690,15 @@ __global__ void k_r1_moments(const R1Dev *__restrict__ cases, int c_idx) {
 }
 
 template <int RM, int D, int TS>
-static void r1_steps(const R1Dev *cases, const int2 *m, int nblocks, const int2 *mn, int nn, size_t ldsn,
-                     long nsteps, hipStream_t s) {
-  for (long k = 0; k < nsteps; k++) {
-    if (nn > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nn), dim3(512), ldsn, s, cases, mn, 1);
-    hipLaunchKernelGGL((k_r1_stage<1, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
-    if (nn > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nn), dim3(512), ldsn, s, cases, mn, 2);
-    hipLaunchKernelGGL((k_r1_stage<2, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
-    if (nn > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nn), dim3(512), ldsn, s, cases, mn, 3);
-    hipLaunchKernelGGL((k_r1_stage<3, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
-  }
+static void r1_launch(int stage, const R1Dev *cases, const int2 *m, int nblocks, hipStream_t s) {
+  if (stage == 1) hipLaunchKernelGGL((k_r1_stage<1, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
+  else if (stage == 2) hipLaunchKernelGGL((k_r1_stage<2, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
+  else hipLaunchKernelGGL((k_r1_stage<3, RM, D, TS>), dim3(nblocks), dim3(512), 0, s, cases, m);
 }
 
-// cells per block: 32 up to 128 rows, 16 above; maps that would have at most
-// SMALL_TABLE_MAP blocks take CTILE_SMALL cells per block (latency-bound sizes)
+// cells per block: 32 up to 128 rows, 16 up to 256, 4 above; maps of at most
+// 256 rows that would have at most SMALL_TABLE_MAP blocks take CTILE_SMALL
+// cells per block (latency-bound sizes)
 int r1_tile(int rmax, int total_cells) {
   if (rmax > R1_RMAX) return R1_TILE_BIG;
   const int t = rmax <= 128 ? R1_TILE : R1_TILE_2;
@@ -1710,36 +1706,55 @@ int r1_tile(int rmax, int total_cells) {
 }
 
 template <int RM, int D>
-static hipError_t r1_by_tile(const R1Dev *cases, const int2 *m, int nblocks, int tile, const int2 *mn, int nn,
-                             size_t ldsn, long nsteps, hipStream_t s) {
+static bool r1_by_tile(int stage, const R1Dev *cases, const int2 *m, int nblocks, int tile, hipStream_t s) {
   if constexpr (RM > R1_RMAX) {
     // the largest row counts take 4-cell tiles only (the LDS holds RM rows)
-    if (tile != R1_TILE_BIG) return hipErrorInvalidValue;
-    r1_steps<RM, D, R1_TILE_BIG>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
+    if (tile != R1_TILE_BIG) return false;
+    r1_launch<RM, D, R1_TILE_BIG>(stage, cases, m, nblocks, s);
   } else {
     constexpr int TL = RM <= 128 ? R1_TILE : R1_TILE_2;
-    if (tile == TL) r1_steps<RM, D, TL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
-    else if (tile == CTILE_SMALL) r1_steps<RM, D, CTILE_SMALL>(cases, m, nblocks, mn, nn, ldsn, nsteps, s);
-    else return hipErrorInvalidValue;
+    if (tile == TL) r1_launch<RM, D, TL>(stage, cases, m, nblocks, s);
+    else if (tile == CTILE_SMALL) r1_launch<RM, D, CTILE_SMALL>(stage, cases, m, nblocks, s);
+    else return false;
   }
-  return hipGetLastError();
+  return true;
 }
 
-hipError_t launch_r1_step(const R1Dev *cases, const int *map, int nblocks, int rmax, int dim, int tile,
-                          const int *map_n, int nblocks_n, size_t lds_n, long nsteps, hipStream_t s) {
-  if (nblocks <= 0) return hipSuccess;
-  if (nblocks_n > 0 && (lds_n == 0 || lds_n > NBAR_LDS_MAX)) return hipErrorInvalidValue;
-  const int2 *m = (const int2 *)map, *mn = (const int2 *)map_n;
+// one stage of one group: the instantiation that holds the group's rows
+static bool r1_group_stage(int stage, const R1Dev *cases, const R1Group &g, int dim, hipStream_t s) {
+  const int2 *m = (const int2 *)g.map;
   if (dim == 1) {
-    if (rmax <= 64) return r1_by_tile<64, 1>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
-    if (rmax <= 4 * MAXQH) return r1_by_tile<4 * MAXQH, 1>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
+    if (g.rmax <= 64) return r1_by_tile<64, 1>(stage, cases, m, g.nblocks, g.tile, s);
+    if (g.rmax <= 4 * MAXQH) return r1_by_tile<4 * MAXQH, 1>(stage, cases, m, g.nblocks, g.tile, s);
   } else if (dim == 2) {
-    if (rmax <= 128) return r1_by_tile<128, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
-    if (rmax <= R1_RMAX) return r1_by_tile<R1_RMAX, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
-    if (rmax <= R1_RMAX_BIG)
-      return r1_by_tile<R1_RMAX_BIG, 2>(cases, m, nblocks, tile, mn, nblocks_n, lds_n, nsteps, s);
+    if (g.rmax <= 128) return r1_by_tile<128, 2>(stage, cases, m, g.nblocks, g.tile, s);
+    if (g.rmax <= R1_RMAX) return r1_by_tile<R1_RMAX, 2>(stage, cases, m, g.nblocks, g.tile, s);
+    if (g.rmax <= R1_RMAX_BIG) return r1_by_tile<R1_RMAX_BIG, 2>(stage, cases, m, g.nblocks, g.tile, s);
   }
-  return hipErrorInvalidValue;
+  return false;
+}
+
+hipError_t launch_r1_step(const R1Dev *cases, const R1Group *groups, int ngroups, int dim, const int *map_n,
+                          int nblocks_n, size_t lds_n, long nsteps, hipStream_t s) {
+  if (nblocks_n > 0 && (lds_n == 0 || lds_n > NBAR_LDS_MAX)) return hipErrorInvalidValue;
+  const int2 *mn = (const int2 *)map_n;
+  // check every group's launch shape before the first launch
+  for (int gi = 0; gi < ngroups; gi++) {
+    const R1Group &g = groups[gi];
+    if (g.nblocks == 0) continue;
+    if (g.nblocks < 0 || !g.map || g.rmax <= 0 || g.rmax > (dim == 1 ? 4 * MAXQH : R1_RMAX_BIG)) return hipErrorInvalidValue;
+    if (g.rmax > R1_RMAX ? g.tile != R1_TILE_BIG
+                         : (g.tile != CTILE_SMALL && g.tile != (g.rmax <= 128 ? R1_TILE : R1_TILE_2)))
+      return hipErrorInvalidValue;
+  }
+  for (long k = 0; k < nsteps; k++)
+    for (int stage = 1; stage <= 3; stage++) {
+      if (nblocks_n > 0) hipLaunchKernelGGL(k_r1_nbar, dim3(nblocks_n), dim3(512), lds_n, s, cases, mn, stage);
+      // the groups hold different cases: their launches of a stage are independent
+      for (int gi = 0; gi < ngroups; gi++)
+        if (groups[gi].nblocks > 0 && !r1_group_stage(stage, cases, groups[gi], dim, s)) return hipErrorInvalidValue;
+    }
+  return hipGetLastError();
 }
 
 hipError_t launch_r1_moments(const R1Dev *cases, int c, int nx, hipStream_t s) {

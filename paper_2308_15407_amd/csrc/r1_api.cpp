@@ -29,13 +29,12 @@ struct fdlb_r1_ctx {
   hipStream_t stream = nullptr;
   R1Dev *d_cases = nullptr;
   int *d_map = nullptr;
-  int nmap = 0;
+  R1Group grp[2] = {};   // cases of at most R1_RMAX rows, then the larger ones
   int rmax = 0;    // the largest row count of the cases
   int *d_mapN = nullptr;   // averaged-density blocks of the chi_mode 1 cases
   int nN = 0;
   size_t ldsN = 0;
   int dim = 0;     // 1 or 2, the same for every case
-  int tile = R1_TILE;
 };
 
 static size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
@@ -149,15 +148,19 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
   std::vector<int> map, mapN;
   auto bail = [&](int code) { delete h; return code; };
   h->dim = r1_dim(cases[0]);
-  int cells = 0;
+  int cells[2] = {0, 0};
   for (int i = 0; i < ncases; i++) {
     CaseHost &c = h->cases[i];
     std::string why;
     if (r1_case(cases[i], c, why)) return bail(api_fail(FDLB_EINVAL, why));
-    h->rmax = std::max(h->rmax, r1_rows(c, h->dim));
-    cells += c.nx;
+    const int rows = r1_rows(c, h->dim), g = rows > R1_RMAX;
+    h->rmax = std::max(h->rmax, rows);
+    h->grp[g].rmax = std::max(h->grp[g].rmax, rows);
+    cells[g] += c.nx;
   }
-  h->tile = r1_tile(h->rmax, cells);
+  for (int g = 0; g < 2; g++)
+    if (cells[g] > 0) h->grp[g].tile = r1_tile(h->grp[g].rmax, cells[g]);
+  std::vector<int> mapg[2];
   for (int i = 0; i < ncases; i++) {
     CaseHost &c = h->cases[i];
     const int nx = c.nx, Q = c.qh, Q2 = 2 * Q, qy = h->dim == 2 ? c.qy : 1, Kh = Q2 * qy, R = 2 * Kh;
@@ -209,7 +212,9 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
     r1_fill(c, fields.data(), nullptr, f);
     R1CHK(hipMemcpyAsync(d.f, f.data(), sizeof(double) * f.size(), hipMemcpyHostToDevice, h->stream));
     R1CHK(hipStreamSynchronize(h->stream));
-    for (size_t t = 0; t < r1_tiles(c, h->tile); t++) { map.push_back(i); map.push_back((int)t); }
+    R1Group &grp = h->grp[r1_rows(c, h->dim) > R1_RMAX];
+    std::vector<int> &mg = mapg[&grp - h->grp];
+    for (size_t t = 0; t < r1_tiles(c, grp.tile); t++) { mg.push_back(i); mg.push_back((int)t); }
     if (c.p.chi_mode == 1) {
       // averaged-density blocks: the LDS holds the densities and faces of a tile's window
       for (int t = 0; t * NBAR_TILE < nx; t++) {
@@ -220,8 +225,13 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
       }
     }
   }
+  map = mapg[0];
+  map.insert(map.end(), mapg[1].begin(), mapg[1].end());
   h->d_map = (int *)take(sizeof(int) * map.size());
-  h->nmap = (int)(map.size() / 2);
+  h->grp[0].map = h->d_map;
+  h->grp[0].nblocks = (int)(mapg[0].size() / 2);
+  h->grp[1].map = h->d_map + mapg[0].size();
+  h->grp[1].nblocks = (int)(mapg[1].size() / 2);
   h->nN = (int)(mapN.size() / 2);
   if (h->nN > 0) h->d_mapN = (int *)take(sizeof(int) * mapN.size());
   if (off > bytes) return bail(api_fail(FDLB_ENOMEM, "workspace layout exceeds the buffer"));
@@ -237,8 +247,7 @@ extern "C" int fdlb_r1_init(const fdlb_params *cases, int ncases, void *dev_work
 
 extern "C" int fdlb_r1_step(fdlb_r1_handle h, long nsteps) {
   if (!h || nsteps < 0) return api_fail(FDLB_EINVAL, "null handle or negative step count");
-  R1CHK(launch_r1_step(h->d_cases, h->d_map, h->nmap, h->rmax, h->dim, h->tile, h->d_mapN, h->nN, h->ldsN, nsteps,
-                       h->stream));
+  R1CHK(launch_r1_step(h->d_cases, h->grp, 2, h->dim, h->d_mapN, h->nN, h->ldsN, nsteps, h->stream));
   return FDLB_OK;
 }
 
