@@ -1,15 +1,21 @@
 """Benchmark: node-velocity updates per second of the FDLB time step on one MI355X.
 
-Workload (default): the plain Couette configuration -- Nx = 256 wall-refined
-cells, 2x8 half-range x 4 x 4 full-range velocities (K = 256), Kn = 0.1,
-eta0 = 0.2, walls T = 1 moving at u_y = -/+0.2, Shakhov Pr = 2/3, FP64.  One
-step = one TVD-RK3 step (three stages of table + update launches) of the whole
-case; inputs are resident in device memory before timing starts.
+Workload (default): the plain force-driven Poiseuille configuration, the
+largest single-GPU case -- Nx = 512 wall-refined cells, 2x16 half-range x 6 x 4
+full-range velocities (K = 768), Kn = 0.05, eta0 = 0.3, a_y = 0.05, walls T = 1
+at rest, Shakhov with the dense Prandtl number, FP64.  One step = one TVD-RK3
+step (three stages of table + update launches) of the whole case; inputs are
+resident in device memory before timing starts.
 
-Also reported: the FP32-bulk variant of the same case, a large single case
-(Nx = 32768, K = 512) that sizes the memory-bound roofline, the roofline
-object for the dominant kernel (the update launch of RK stage 2) with its
-time measured by HIP events, and the CPU oracle timed on this host.
+Also reported: the FP32-bulk variant of the same case, the Couette case (Nx =
+256, K = 256), a large single case (Nx = 32768, K = 512) that sizes the
+memory-bound roofline, the sweeps, the reduced models, time to steady state,
+the roofline object for the dominant kernel (its time measured by HIP events
+on the solver's stream), and the CPU oracle timed on this host's cores.
+
+--profile-case WORKLOAD runs a short fixed run for profilers instead (no JSON
+line): one untimed step, --steps steps, then a plain device copy of --copy-mib
+MiB that calibrates memory-traffic counters.
 """
 import argparse
 import hashlib
@@ -24,20 +30,38 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0
 
 
+WORKLOADS = {
+    "C1": "C1 Fourier: Nx=64 uniform, 2x4 half-range x 3 x 3 (K=72), Kn=0.1, eta0=0.05, walls T=1.0/1.1 at rest, "
+          "BGK + J1",
+    "C2": "C2 Couette: Nx=256 tanh-stretched, 2x8 half-range x 4 x 4 (K=256), Kn=0.1, eta0=0.2, walls T=1 at "
+          "u_y=-/+0.2, Shakhov Pr=2/3",
+    "C3": "C3 Poiseuille: Nx=512 tanh-stretched, 2x16 half-range x 6 x 4 (K=768), Kn=0.05, eta0=0.3, a_y=0.05, "
+          "walls T=1 at rest, Shakhov dense Pr",
+    "R2": "R2 Fourier: Nx=32768 uniform, 2x16 half-range x 4 x 4 (K=512), Kn=0.1, eta0=0.05, walls T=1.0/1.1, BGK + J1",
+}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=100)
-    ap.add_argument("--workload", default="C2")
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the main workload")
     ap.add_argument("--large-steps", type=int, default=60)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=100)
     ap.add_argument("--r1-steps", type=int, default=20)
-    ap.add_argument("--tts-batch", type=int, default=64, help="held-out cases in the learned time-to-steady leg")
-    ap.add_argument("--tts-seq", type=int, default=8, help="cases solved one at a time by the plain FP64 leg")
+    ap.add_argument("--tts-cases", type=int, default=16,
+                    help="held-out cases of the time-to-steady leg (every arm solves the same cases)")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the all-cores oracle sample")
+    # profiler mode
+    ap.add_argument("--profile-case", default=None, help="short fixed run of a workload (R2, C2, C3, sweep)")
+    ap.add_argument("--precision", type=int, default=0)
+    ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("KX_PER_CHUNK", "WAVES"))
+    ap.add_argument("--copy-mib", type=int, default=256)
+    ap.add_argument("--reduced", action="store_true", help="profile the reduced 1D/2D form of the workload")
     return ap.parse_args()
 
 
@@ -89,33 +113,77 @@ def measure(cfg, steps, warmup, retune, graph_steps=50):
     return s, ms, nodes, tile, prof
 
 
-def roofline(prof, nodes, prec, kernel_name, workload):
-    """The kernel whose bytes scale with the nodes: the stage-2 update (reads
-    f^(1) and f^n, writes f^(2)): 3 passes x bytes per population x nodes,
-    algorithmic.  (At small sizes the per-cell table pass can take as long,
-    as a latency chain of little traffic.)"""
+def update_roofline(prof, nodes, prec, workload):
+    """The stage-2 update (reads f^(1) and f^n, writes f^(2)): 3 passes x bytes
+    per population x nodes, algorithmic, over its mean launch time."""
     s_bytes = 8 if prec == 0 else 4
     t_ms = prof[2] if prec == 0 else prof[5]
+    kernel = "k_update<%s,2>" % ("double" if prec == 0 else "float")
     alg = 3.0 * s_bytes * nodes
     achieved = alg / (t_ms * 1e-3) / 1e9
     return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(kernel_name, workload),
-            "kernel": kernel_name, "launch_ms": round(t_ms, 5), "algorithmic_bytes_per_launch": alg}
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(kernel, workload),
+            "kernel": kernel, "launch_ms": round(t_ms, 5), "algorithmic_bytes_per_launch": alg}
 
 
-def cpu_baseline(cfg, budget_s=15.0):
+def table_roofline(prof, cases, prec, workload, chunks):
+    """The table pass (per cell: moments from the chunk partials, closure,
+    gradients, projection tables): it reads 9 FP64 raw sums per cell and chunk
+    and writes 4 (2 Q_x^h + Q_y Q_z) table values plus 1/tau per cell."""
+    s_bytes = 8 if prec == 0 else 4
+    alg = 0.0
+    for c, nch in zip(cases, chunks):
+        alg += 8.0 * 9 * nch * c["nx"] + s_bytes * (4 * (2 * c["qx_half"] + c["qy"] * c["qz"]) + 1) * c["nx"]
+    t_ms = prof[0]
+    achieved = alg / (t_ms * 1e-3) / 1e9
+    kernel = "k_table<%s>" % ("double" if prec == 0 else "float")
+    return {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": read_traffic(kernel, workload),
+            "kernel": kernel, "launch_ms": round(t_ms, 5), "algorithmic_bytes_per_launch": alg}
+
+
+def dominant_roofline(tile, prof, cfg, nodes, prec, workload):
+    """Roofline object of the kernel that takes the largest share of a step:
+    the stage-2 update or the table pass (three launches per step each)."""
+    upd = update_roofline(prof, nodes, prec, workload)
+    cases = cfg if isinstance(cfg, list) else [cfg]
+    kxc = tile[0]
+    chunks = [-(-2 * c["qx_half"] // min(kxc, 2 * c["qx_half"])) for c in cases]
+    tab = table_roofline(prof, cases, prec, workload, chunks)
+    up_ms = sum(prof[1 + 3 * prec:4 + 3 * prec])
+    dom, other = (tab, upd) if 3 * prof[0] > up_ms else (upd, tab)
+    dom = dict(dom)
+    dom["share_of_kernel_time"] = round((3 * prof[0] if dom is tab else up_ms) / (3 * prof[0] + up_ms), 3)
+    dom["other_kernel"] = other
+    return dom
+
+
+def cpu_baseline(cfg, budget_s=12.0, single_s=4.0):
+    """The FP64 oracle on this host: all cores (OpenMP over cells and
+    velocities), then one thread, each on a bounded number of steps of the
+    same case."""
     from oracle import oracle as O
-    o = O.Oracle(**{k: v for k, v in cfg.items() if k != "precision"})
-    t0 = time.perf_counter()
-    o.step(1)
-    one = time.perf_counter() - t0
-    n = max(1, min(2000, int(budget_s / max(one, 1e-6))))
-    t0 = time.perf_counter()
-    o.step(n)
-    dt = time.perf_counter() - t0
-    nodes = cfg["nx"] * o.K
-    return {"value": nodes * n / dt, "unit": "node-velocity updates/s", "cores": 1, "kind": "oracle",
-            "sample": "%d RK3 steps of the same case (Nx=%d, K=%d) on one host thread, %.1f s" % (n, cfg["nx"], o.K, dt)}
+    L = O.lib()
+    cores = L.orc_threads()
+    res = {}
+    for label, threads, budget in (("all", cores, budget_s), ("one", 1, single_s)):
+        L.orc_set_threads(threads)
+        o = O.Oracle(**{k: v for k, v in cfg.items() if k != "precision"})
+        t0 = time.perf_counter()
+        o.step(1)
+        one = time.perf_counter() - t0
+        n = max(1, min(2000, int(budget / max(one, 1e-6))))
+        t0 = time.perf_counter()
+        o.step(n)
+        dt = time.perf_counter() - t0
+        res[label] = (cfg["nx"] * o.K * n / dt, n, dt)
+    L.orc_set_threads(cores)
+    v, n, dt = res["all"]
+    v1, n1, dt1 = res["one"]
+    return {"value": round(v, 1), "unit": "node-velocity updates/s", "cores": cores, "kind": "oracle",
+            "sample": "%d RK3 steps of the same case (Nx=%d, K=%d) on %d host threads, %.1f s" %
+                      (n, cfg["nx"], 2 * cfg["qx_half"] * cfg["qy"] * cfg["qz"], cores, dt),
+            "single_thread": {"value": round(v1, 1), "sample": "%d steps on one thread, %.1f s" % (n1, dt1)}}
 
 
 def sweep_leg(steps, retune):
@@ -179,12 +247,12 @@ def reduced_leg(steps, workload="R2", warmup=5):
             "values": vals, "effective_GBps_whole_step": round(eff, 1), "frac_of_hbm_peak": round(eff / HBM_PEAK_GBS, 4)}
 
 
-def time_to_steady_leg(n_batch, n_seq, tol=1e-8, max_steps=400000):
-    """Wall-clock time to r < tol per case: plain FP64 cold start (one case at a
-    time, a sample of n_seq cases) against batched FP32 bulk + learned warm
-    start (n_batch held-out cases in one batch, inference included)."""
+def time_to_steady_leg(n_cases, tol=1e-8, max_steps=400000):
+    """Wall-clock time to r < tol per case on one sample of held-out cases:
+    plain FP64 cold start (one case at a time) against the batched arms (all
+    the sample's cases in one batch, FP32 bulk or FP64, cold or learned warm
+    start with inference included)."""
     import numpy as np
-    import torch
     from paper_2308_15407_amd import learned as LW
     path = LW.default_weights_path()
     if not os.path.exists(path):
@@ -193,10 +261,10 @@ def time_to_steady_leg(n_batch, n_seq, tol=1e-8, max_steps=400000):
     evp = LW.default_eval_path()
     if not os.path.exists(evp):
         return {"skipped": "no held-out evaluation summary next to the weights"}
-    # held-out cases that the plain FP64 solve converges on (fixed by the evaluation)
-    held = LW.cases_from_seeds(json.load(open(evp))["seeds"][:n_batch])
+    ev = json.load(open(evp))
+    held = LW.cases_from_seeds(ev["seeds"][:n_cases])
     seq_t, seq_st = [], []
-    for c in held[:n_seq]:
+    for c in held:
         _, _, st, res, wall = LW.solve_steady([c], tol, max_steps, check_every=100, precision=0)
         seq_t.append(wall)
         seq_st.append(int(st[0]))
@@ -212,11 +280,46 @@ def time_to_steady_leg(n_batch, n_seq, tol=1e-8, max_steps=400000):
         arms[name] = {"s_per_case": round(wall / len(held), 5), "mean_steps": float(np.mean(st)),
                       "converged": int(np.sum(res < tol)), "fallbacks": int(nfb)}
     plain = float(np.mean(seq_t))
-    return {"workload": "held-out sweep cases (first %d of the evaluation set): Nx=64 uniform, Q_x^h<=8 x 4 x 4, "
-                        "Kn>=0.05, tol %g" % (len(held), tol),
-            "plain_fp64_cold_s_per_case": round(plain, 4), "plain_sample_cases": len(seq_t),
-            "plain_mean_steps": float(np.mean(seq_st)), "batched": arms,
-            "speedup_batched_fp32_learned_vs_plain": round(plain / arms["batched_fp32_learned"]["s_per_case"], 2)}
+    return {"workload": "the first %d held-out cases of the warm-start evaluation set (%s), tol %g; every arm "
+                        "solves these same cases" % (len(held), ev.get("generator", "C4 generator"), tol),
+            "plain_fp64_cold_s_per_case": round(plain, 4), "plain_mean_steps": float(np.mean(seq_st)),
+            "batched": arms,
+            "speedup_batched_fp32_learned_vs_plain": round(plain / arms["batched_fp32_learned"]["s_per_case"], 2),
+            "speedup_learned_vs_cold_batched_fp32": round(arms["batched_fp32_cold"]["s_per_case"] /
+                                                          arms["batched_fp32_learned"]["s_per_case"], 3)}
+
+
+def profile_case(a):
+    """Short fixed run of one workload for rocprofv3 (kernel traces, counters)."""
+    import torch
+    import fdlb_inputs as I
+    from paper_2308_15407_amd import fdlb as F
+    from paper_2308_15407_amd.solver import ReducedSolver, Solver
+    if a.reduced:
+        s = ReducedSolver(I.config(a.profile_case, precision=0))
+    else:
+        if a.profile_case == "sweep":
+            from paper_2308_15407_amd import sweep
+            cfg = sweep.sweep_cases(256, precision=a.precision)
+        else:
+            cfg = I.config(a.profile_case, precision=a.precision)
+        s = Solver(cfg)
+        if a.tiling:
+            s.set_tiling(*a.tiling)
+        else:
+            from paper_2308_15407_amd import autotune
+            autotune.tune(s)
+    s.step(1)
+    torch.cuda.synchronize()
+    s.step(a.steps)
+    torch.cuda.synchronize()
+    if a.copy_mib > 0:
+        n = a.copy_mib << 20
+        buf = torch.empty(2 * n, dtype=torch.uint8, device="cuda")
+        F.fdlb_copy_probe(buf.data_ptr(), buf.data_ptr() + n, n, torch.cuda.current_stream().cuda_stream)
+        torch.cuda.synchronize()
+    print("profile case done: %s%s precision %d, %d steps" % (a.profile_case, " reduced" if a.reduced else "",
+                                                              a.precision, a.steps), flush=True)
 
 
 def main():
@@ -228,7 +331,11 @@ def main():
     import torch
     import fdlb_inputs as I
     assert torch.cuda.is_available(), "bench.py needs a HIP device"
-    cfg = I.config(args.workload, precision=0)
+    if args.profile_case:
+        profile_case(args)
+        return
+    wl = args.workload
+    cfg = I.config(wl, precision=0)
     s, ms, nodes, tile, prof = measure(cfg, args.steps, args.warmup, args.retune)
     value = nodes / (ms * 1e-3)
     out = {
@@ -239,31 +346,47 @@ def main():
         "ms_per_step": round(ms, 6),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f64", "data": "synthetic",
-        "config": {"workload": "%s Couette: Nx=256 tanh-stretched, 2x8 half-range x 4 x 4 (K=256), Kn=0.1, "
-                               "eta0=0.2, walls T=1 at u_y=-/+0.2, Shakhov Pr=2/3, FP64" % args.workload,
-                   "nodes": nodes, "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}},
-        "roofline": roofline(prof, nodes, 0, "k_update<double,2>", args.workload),
+        "config": {"workload": WORKLOADS[wl] + ", FP64", "nodes": nodes,
+                   "tiling": {"kx_per_chunk": tile[0], "waves": tile[1]}},
+        "roofline": dominant_roofline(tile, prof, cfg, nodes, 0, wl),
+        "kernel_ms": {"table": round(prof[0], 5), "update": [round(x, 5) for x in prof[1:4]]},
     }
+    del s
     if not args.no_extra:
-        cfg32 = I.config(args.workload, precision=1)
-        _, ms32, _, tile32, prof32 = measure(cfg32, args.steps, args.warmup, args.retune)
-        out["fp32_bulk"] = {"value": round(nodes / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 6),
-                            "roofline": roofline(prof32, nodes, 1, "k_update<float,2>", args.workload)}
+        cfg32 = I.config(wl, precision=1)
+        s32, ms32, _, tile32, prof32 = measure(cfg32, args.steps, args.warmup, args.retune)
+        del s32
+        out["fp32_bulk"] = {"workload": WORKLOADS[wl] + ", FP32 bulk with FP64 reductions",
+                            "value": round(nodes / (ms32 * 1e-3), 1), "ms_per_step": round(ms32, 6),
+                            "tiling": {"kx_per_chunk": tile32[0], "waves": tile32[1]},
+                            "roofline": dominant_roofline(tile32, prof32, cfg32, nodes, 1, wl),
+                            "kernel_ms": {"table": round(prof32[0], 5), "update": [round(x, 5) for x in prof32[4:7]]}}
+        other = "C2" if wl != "C2" else "C3"
+        for prec in (0, 1):
+            cfgO = I.config(other, precision=prec)
+            sO, msO, nodesO, tileO, profO = measure(cfgO, args.steps, args.warmup, args.retune)
+            del sO
+            out["%s_%s" % (other, "f64" if prec == 0 else "f32")] = {
+                "workload": WORKLOADS[other] + (", FP64" if prec == 0 else ", FP32 bulk"),
+                "value": round(nodesO / (msO * 1e-3), 1), "ms_per_step": round(msO, 6),
+                "roofline": dominant_roofline(tileO, profO, cfgO, nodesO, prec, other)}
         for prec in (0, 1):
             cfgL = I.config("R2", precision=prec)
-            _, msL, nodesL, tileL, profL = measure(cfgL, args.large_steps, 5, args.retune, graph_steps=10)
+            sL, msL, nodesL, tileL, profL = measure(cfgL, args.large_steps, 5, args.retune, graph_steps=10)
+            del sL
             out["large_case_" + ("f64" if prec == 0 else "f32")] = {
-                "workload": "Fourier Nx=32768 uniform, 2x16 x 4 x 4 (K=512), %s" % ("FP64" if prec == 0 else "FP32 bulk"),
+                "workload": WORKLOADS["R2"] + (", FP64" if prec == 0 else ", FP32 bulk"),
                 "value": round(nodesL / (msL * 1e-3), 1), "ms_per_step": round(msL, 5),
+                "effective_GBps_whole_step": round(8 * (8 if prec == 0 else 4) * nodesL / (msL * 1e-3) / 1e9, 1),
                 "tiling": {"kx_per_chunk": tileL[0], "waves": tileL[1]},
-                "roofline": roofline(profL, nodesL, prec, "k_update<%s,2>" % ("double" if prec == 0 else "float"), "R2"),
+                "roofline": update_roofline(profL, nodesL, prec, "R2"),
                 "kernel_ms": {"table": round(profL[0], 5), "update": [round(x, 5) for x in profL[1 + 3 * prec:4 + 3 * prec]]}}
         out["reduced_1d"] = reduced_leg(args.large_steps, "R2")
         out["reduced_2d"] = reduced_leg(args.steps, "C2", warmup=args.warmup)
         out["sweep"] = sweep_leg(args.sweep_steps, args.retune)
         out["sweep_r1"] = sweep_r1_leg(args.r1_steps, args.retune)
-        out["time_to_steady"] = time_to_steady_leg(args.tts_batch, args.tts_seq)
-    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg)
+        out["time_to_steady"] = time_to_steady_leg(args.tts_cases)
+    out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg, budget_s=args.cpu_seconds)
     print(json.dumps(out))
 
 

@@ -129,8 +129,11 @@ int fdlb_dt(fdlb_handle h, int c, double *dt);
    drops below tol, checked every check_every steps (converged cases stop
    advancing).  steps_out[ncases] and resid_out[ncases] receive the step
    count and last residual.  Returns FDLB_ESTALL if some case did not
-   converge within max_steps (outputs still filled).  In FDLB_F32_BULK mode a
-   case whose residual stalls is promoted to FP64 storage and continues. */
+   converge within max_steps (outputs still filled).  An FDLB_F32_BULK case
+   is promoted to FP64 storage, with the mass it started the call with, when
+   its residual stalls (fdlb_set_stall_checks), falls below tol or reaches
+   exactly 0 (a fixed point of the FP32 map, whose sub-ulp increments are
+   lost), and finishes in FP64: the converged state is an FP64 one. */
 int fdlb_run_to_steady(fdlb_handle h, double tol, long max_steps, long check_every,
                        long *steps_out, double *resid_out);
 

@@ -57,3 +57,41 @@ def loss_grad(params, shapes, x, t):
             d = (d @ W) * gelu_d(zs[i - 1])
     flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
     return np.mean((y - t) ** 2), flat
+
+
+def bf16(a):
+    """Round to bfloat16 (nearest, ties to even) through float32, returned as
+    float64: the value the GPU keeps when it stores a BF16 operand."""
+    u = np.asarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def loss_grad_bf16(params, shapes, x, t, rnd=bf16):
+    """The same network with the storage precision of the GPU path: the matrix
+    products take BF16 operands (the input, the weights, the hidden
+    activations GELU(z) and the back-propagated errors dL/dz) and accumulate
+    exactly; biases, pre-activations, the loss and the bias gradients stay
+    unrounded.  With rnd the identity this is loss_grad."""
+    layers = unpack(np.asarray(params, dtype=np.float64), shapes)
+    t = np.asarray(t, dtype=np.float64)
+    Wr = [rnd(W) for W, _ in layers]
+    h = rnd(np.asarray(x, dtype=np.float64))
+    hs, zs = [h], []
+    for i, (W, b) in enumerate(layers):
+        z = h @ Wr[i].T + b
+        zs.append(z)
+        if i + 1 < len(layers):
+            h = rnd(gelu(z))
+            hs.append(h)
+    y = zs[-1]
+    n = y.size
+    d = 2.0 * (y - t) / n          # unrounded error of the output layer
+    grads = [None] * len(layers)
+    for i in range(len(layers) - 1, -1, -1):
+        db_ = rnd(d)
+        grads[i] = (db_.T @ hs[i], d.sum(axis=0))
+        if i > 0:
+            d = (db_ @ Wr[i]) * gelu_d(zs[i - 1])
+    flat = np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
+    return np.mean((y - t) ** 2), flat

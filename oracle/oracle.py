@@ -19,7 +19,7 @@ def build(force=False):
     """Compile the oracle (gcc, -O2, no FP contraction)."""
     if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
         tmp = _LIB + ".tmp%d" % os.getpid()
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fPIC", "-shared", "-o", tmp,
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared", "-o", tmp,
                                _SRC, "-lquadmath", "-lm"])
         os.replace(tmp, _LIB)
     return _LIB
@@ -49,6 +49,9 @@ def lib():
         L.orc_create.restype = P
         L.orc_create.argtypes = [C.POINTER(OrcParams)]
         L.orc_destroy.argtypes = [P]
+        L.orc_threads.restype = I
+        L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [I]
         for name, res in [("orc_K", I), ("orc_dt", D), ("orc_sigma", D), ("orc_Lc", D), ("orc_steps", C.c_long)]:
             getattr(L, name).restype = res
             getattr(L, name).argtypes = [P]
@@ -65,6 +68,7 @@ def lib():
         L.orc_lattice.argtypes = [P, dp, dp, dp, dp]
         L.orc_grid.argtypes = [P, dp, dp]
         L.orc_rhs.argtypes = [P, dp, dp]
+        L.orc_face_fluxes.argtypes = [P, dp, dp, dp]
         L.orc_gh_rule.restype = I
         L.orc_gh_rule.argtypes = [I, dp, dp]
         L.orc_hr_rule.restype = I
@@ -202,6 +206,13 @@ class Oracle:
         nw = np.zeros(2)
         lib().orc_rhs(self._h, out, nw)
         return out, nw
+
+    def face_fluxes(self):
+        """Numerical face fluxes of the current state, each [nx + 1]: mass
+        sum p_x f^, x-momentum sum p_x^2 f^ and y-momentum sum p_x p_y f^."""
+        m, px, py = (np.zeros(self.nx + 1) for _ in range(3))
+        lib().orc_face_fluxes(self._h, m, px, py)
+        return m, px, py
 
     def kmat(self):
         out = np.zeros(self.params["qy"] ** 2)

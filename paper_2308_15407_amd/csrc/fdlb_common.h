@@ -61,6 +61,8 @@ struct LatOff {
                     // holds f - bg
   int kbg;          // body-force kernel applied to the background [K]
   int bgm;          // raw moment sums of the background [NRAW]
+  int xbg, yzbg;    // factors of the background, bg[kappa] = xbg[kx] yzbg[ky*qz+kz]: n_init X^0[kx]
+                    // [2qh] and Y^0[ky] Z^0[kz] [qyz]; FP32 tables hold n X_0 - xbg and YZ_0 - yzbg
   int total;
 };
 

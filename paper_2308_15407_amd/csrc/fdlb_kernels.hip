@@ -55,14 +55,15 @@ __device__ __forceinline__ void stb(GAS T *row, unsigned bytes, T v) {
 __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc_of(const GAS void *row, unsigned bytes) {
   return __builtin_amdgcn_make_buffer_rsrc((void *)row, (short)0, (int)bytes, 0x00020000);
 }
+// off: the lane's byte offset; soff: a wave-uniform byte offset (a row)
 template <typename T>
-__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, unsigned off) {
+__device__ __forceinline__ T bld(__amdgpu_buffer_rsrc_t r, unsigned off, int soff = 0) {
   if constexpr (sizeof(T) == 8) {
     typedef int v2i __attribute__((ext_vector_type(2)));
-    const v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+    const v2i v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, soff, 0);
     return __builtin_bit_cast(T, v);
   } else {
-    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, 0, 0));
+    return __builtin_bit_cast(T, __builtin_amdgcn_raw_buffer_load_b32(r, (int)off, soff, 0));
   }
 }
 template <typename T>
@@ -72,6 +73,27 @@ __device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, T v)
     __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, (int)off, 0, 0);
   } else {
     __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, 0, 0);
+  }
+}
+template <typename T>
+__device__ __forceinline__ void bst(__amdgpu_buffer_rsrc_t r, unsigned off, int soff, T v) {
+  if constexpr (sizeof(T) == 8) {
+    typedef int v2i __attribute__((ext_vector_type(2)));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(v2i, v), r, (int)off, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)off, soff, 0);
+  }
+}
+// value of lane + 1 (lane 63 receives 0): a wave-wide DPP shift
+template <typename T>
+__device__ __forceinline__ T shift_down1(T v) {
+  if constexpr (sizeof(T) == 8) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_mov_dpp((int)b, 0x130, 0xf, 0xf, true);
+    const int hi = __builtin_amdgcn_mov_dpp((int)(b >> 32), 0x130, 0xf, 0xf, true);
+    return __builtin_bit_cast(T, ((long long)hi << 32) | (unsigned)lo);
+  } else {
+    return __builtin_bit_cast(T, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), 0x130, 0xf, 0xf, true));
   }
 }
 
@@ -568,12 +590,15 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   __syncthreads();
 
   // ---- n X_a[kx] and YZ_a[ky,kz] tables, one flat item list ----
+  // layout [kx][cell][a] and [yz][cell][a]: the four coefficients of a node
+  // and cell are adjacent, so a reader takes them with one vector load
   // an X item is one cell and half x a pair of nodes: each base weight read
   // from LDS feeds the two dot products and the three base moments m_0..m_2
   const int nkx = c.nkx, qyz = c.qyz;
   constexpr int P = sizeof(T) == 4 ? 1 : 0;   // storage precision of this instantiation
   T *tX = (T *)c.tabX[P];
   T *tYZ = (T *)c.tabYZ[P];
+  typedef T T4 __attribute__((ext_vector_type(4)));
   const int ngrp = (qh + 1) / 2;
   const int nXi = own * 2 * ngrp, nYi = own * qyz;
   for (int it = tid; it < nXi + nYi; it += blockDim.x) {
@@ -612,10 +637,13 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
           const double X1 = dk * x0 + ck * mb[0];
           const double X2 = dk * dk * x0 + ck * (dk * mb[0] + mb[1]);
           const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
-          tX[(size_t)(0 * nkx + kx) * nx + i] = (T)(n * x0);
-          tX[(size_t)(1 * nkx + kx) * nx + i] = (T)(n * sg * X1);
-          tX[(size_t)(2 * nkx + kx) * nx + i] = (T)(n * X2);
-          tX[(size_t)(3 * nkx + kx) * nx + i] = (T)(n * sg * X3);
+          // FP32 storage: the a = 0 table is the deviation from the background factor
+          T4 xv;
+          xv.x = (T)(n * x0 - (sizeof(T) == 4 ? glat[lo.xbg + kx] : 0.0));
+          xv.y = (T)(n * sg * X1);
+          xv.z = (T)(n * X2);
+          xv.w = (T)(n * sg * X3);
+          *(T4 *)(tX + ((size_t)kx * nx + i) * 4) = xv;
         }
       }
     } else {
@@ -633,10 +661,12 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
       const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
       const double yz3 = C[7] * Y[0] * Z0;
       const size_t i = (size_t)c0 + cl;
-      tYZ[(size_t)(0 * qyz + yz) * nx + i] = (T)yz0;
-      tYZ[(size_t)(1 * qyz + yz) * nx + i] = (T)yz1;
-      tYZ[(size_t)(2 * qyz + yz) * nx + i] = (T)yz2;
-      tYZ[(size_t)(3 * qyz + yz) * nx + i] = (T)yz3;
+      T4 yv;
+      yv.x = (T)(yz0 - (sizeof(T) == 4 ? glat[lo.yzbg + yz] : 0.0));
+      yv.y = (T)yz1;
+      yv.z = (T)yz2;
+      yv.w = (T)yz3;
+      *(T4 *)(tYZ + ((size_t)yz * nx + i) * 4) = yv;
     }
   }
   if (tid < own) ((T *)c.invtau[P])[c0 + tid] = (T)s_c[tid][4];
@@ -675,6 +705,15 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 #ifndef FDLB_UPDATE_WPE
 #define FDLB_UPDATE_WPE 4
 #endif
+#ifndef FDLB_UPDATE_WPE_F64
+#define FDLB_UPDATE_WPE_F64 4
+#endif
+// body-force blocks hold every read of a y-line at once (qy rows of stencil,
+// target and f^n values); their maps are small (one block per tile and chunk
+// of a force-driven case), so they trade occupancy for registers
+#ifndef FDLB_UPDATE_WPE_FORCE
+#define FDLB_UPDATE_WPE_FORCE 2
+#endif
 // depth of the row prefetch ring in interior update tiles
 #ifndef FDLB_RING_F64
 #define FDLB_RING_F64 4
@@ -684,7 +723,7 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 #endif
 
 template <typename T, int STAGE, bool FORCE>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_UPDATE_WPE, 8))) k_update(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE ? FDLB_UPDATE_WPE_FORCE : (sizeof(T) == 8 ? FDLB_UPDATE_WPE_F64 : FDLB_UPDATE_WPE), 8))) k_update(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
   extern __shared__ double lds_dyn[];
   // FP32 storage holds the deviation from the case's background populations
   constexpr bool DF = sizeof(T) == 4;
@@ -729,32 +768,40 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
   const size_t fstride = (size_t)c.nxp;          // row stride of the population arrays (slots)
   const int c_qh = c.qh, c_kxc = c.kxc, c_tlds = c.tlds;
   const int lo_px = c.lo.px, lo_py = c.lo.py, lo_pz = c.lo.pz, lo_phi = c.lo.phi, lo_bg = c.lo.bg;
-  // clamped stencil offsets for both upwind directions and ghost flags
-  unsigned op0, op1, op2, op3, op4, on0, on1, on2, on3, on4;
-  bool gp0, gp1, gp2, gn2, gn3, gn4;
-  {
-    const int cp = j - 3, cn = j + 2;
+  // Stencil of the lane's face for one upwind direction (pos: p_x > 0): the
+  // byte offsets of the five upwind-ordered cells, clamped into the row; the
+  // flags of the three that may be ghost cells (only the emitting side of the
+  // stencil can reach past a wall); the face's WENO mode (3: wall face).
+  // Computed where a path needs it, so that interior tiles keep no registers
+  // for it.
+  struct Stencil { unsigned o[5]; bool g[3]; int mode; };
+  auto stencil = [&](bool pos) {
+    Stencil st;
     auto cl = [&](int x) { return (unsigned)fslot(min(max(x, 0), nx - 1)) * (unsigned)sizeof(T); };
-    op0 = cl(cp); op1 = cl(cp + 1); op2 = cl(cp + 2); op3 = cl(cp + 3); op4 = cl(cp + 4);
-    on0 = cl(cn); on1 = cl(cn - 1); on2 = cl(cn - 2); on3 = cl(cn - 3); on4 = cl(cn - 4);
-    // ghosts can only appear on the emitting side of the stencil
-    gp0 = cp < 0; gp1 = cp + 1 < 0; gp2 = cp + 2 < 0;
-    gn2 = cn - 2 >= nx; gn3 = cn - 1 >= nx; gn4 = cn >= nx;
-  }
-  const int mode_p = (j == 0) ? 3 : (j == nx ? 2 : (j == nx - 1 ? 1 : 0));
-  const int mode_n = (j == nx) ? 3 : (j == 0 ? 2 : (j == 1 ? 1 : 0));
+    if (pos) {
+      const int cp = j - 3;
+#pragma unroll
+      for (int k = 0; k < 5; k++) st.o[k] = cl(cp + k);
+      st.g[0] = cp < 0; st.g[1] = cp + 1 < 0; st.g[2] = cp + 2 < 0;
+      st.mode = (j == 0) ? 3 : (j == nx ? 2 : (j == nx - 1 ? 1 : 0));
+    } else {
+      const int cn = j + 2;
+#pragma unroll
+      for (int k = 0; k < 5; k++) st.o[k] = cl(cn - k);
+      st.g[0] = cn >= nx; st.g[1] = cn - 1 >= nx; st.g[2] = cn - 2 >= nx;
+      st.mode = (j == nx) ? 3 : (j == 0 ? 2 : (j == 1 ? 1 : 0));
+    }
+    return st;
+  };
   double acc[NRAW];
 #pragma unroll
   for (int m = 0; m < NRAW; m++) acc[m] = 0.0;
 
-  auto finish = [&](int kap, int ky, int kz, double pxd, T cen, T L) {
+  auto finish = [&](int kap, int ky, int kz, double pxd, T cen, T L, T fnv) {
     const T adv1 = cen + dt * L;
     T o;
     if (STAGE == 1) o = adv1;
-    else {
-      const T fnv = ldb(fn + (size_t)kap * fstride, bcf);
-      o = (STAGE == 2) ? (T)0.75 * fnv + (T)0.25 * adv1 : fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
-    }
+    else o = (STAGE == 2) ? (T)0.75 * fnv + (T)0.25 * adv1 : fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
     if (is_cell) stb(out + (size_t)kap * fstride, bw, o);
     {
       const double pyd = lat[lo_py + ky], pzd = lat[lo_pz + kz];
@@ -772,26 +819,22 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     }
   };
   // face value and cell-centre value of one velocity row (row is uniform)
-  auto face = [&](const GAS T *row, bool pos, T fw, T &cen) -> T {
+  auto face = [&](const GAS T *row, const Stencil &st, bool pos, T fw, T &cen) -> T {
     // unconditional loads at clamped (always valid) cells, then ghost selects
-    if (pos) {
-      const T t0 = ldb(row, op0), t1 = ldb(row, op1), t2 = ldb(row, op2), t3 = ldb(row, op3), t4 = ldb(row, op4);
-      const T v0 = gp0 ? fw : t0, v1 = gp1 ? fw : t1, v2 = gp2 ? fw : t2;
-      cen = t3;
-      const T w = weno_face<T>(v0, v1, v2, t3, t4, mode_p == 3 ? 0 : mode_p);
-      return (mode_p == 3) ? fw : w;
-    } else {
-      const T t0 = ldb(row, on0), t1 = ldb(row, on1), t2 = ldb(row, on2), t3 = ldb(row, on3), t4 = ldb(row, on4);
-      const T v0 = gn4 ? fw : t0, v1 = gn3 ? fw : t1, v2 = gn2 ? fw : t2;
-      cen = v2;
-      const T w = weno_face<T>(v0, v1, v2, t3, t4, mode_n == 3 ? 0 : mode_n);
-      return (mode_n == 3) ? fw : w;
-    }
+    const T t0 = ldb(row, st.o[0]), t1 = ldb(row, st.o[1]), t2 = ldb(row, st.o[2]), t3 = ldb(row, st.o[3]),
+            t4 = ldb(row, st.o[4]);
+    const T v0 = st.g[0] ? fw : t0, v1 = st.g[1] ? fw : t1, v2 = st.g[2] ? fw : t2;
+    cen = pos ? t3 : v2;
+    const T w = weno_face<T>(v0, v1, v2, t3, t4, st.mode == 3 ? 0 : st.mode);
+    return (st.mode == 3) ? fw : w;
   };
-  auto target = [&](int yz, T X0, T X1, T X2, T X3) -> T {
-    const GAS T *t = tYZ + (size_t)yz * tstride;
-    const size_t a = (size_t)qyz * tstride;
-    return X0 * ldb(t, bc) + X1 * ldb(t + a, bc) + X2 * ldb(t + 2 * a, bc) + X3 * ldb(t + 3 * a, bc);
+  // target of one node; FP32: its deviation from the background (see the row loop)
+  typedef T T4 __attribute__((ext_vector_type(4)));
+  auto target = [&](int kx, int yz, T X0, T X1, T X2, T X3) -> T {
+    const T4 y = ldb((const GAS T4 *)(tYZ + (size_t)yz * tstride * 4), 4 * bc);
+    T F = X0 * y.x + X1 * y.y + X2 * y.z + X3 * y.w;
+    if (DF) F += X0 * (T)lat[c.lo.yzbg + yz] + (T)lat[c.lo.xbg + kx] * y.x;
+    return F;
   };
 
   if (!FORCE) {
@@ -804,62 +847,63 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     const int r0 = min(wv * per, nrows), r1 = min(r0 + per, nrows);
     const int rsplit = min(max((c_qh - kx0) * qyz, 0), nrows);
     const int kap_base = kx0 * qyz;
+    // row r of the chunk is (kl, yz) = (r / qyz, r % qyz): r / qyz as the
+    // high word of r * mq with mq = ceil(2^32 / qyz), exact for r < 2^32 / qyz
+    const unsigned mq = (unsigned)((((unsigned long long)1 << 32) + (unsigned)qyz - 1u) / (unsigned)qyz);
     const bool tlds = c_tlds != 0;
+    typedef T T4 __attribute__((ext_vector_type(4)));
     // LDS tables of the tile, four coefficients a = 0..3 adjacent per lane:
     // sYZ[(yz * 64 + lane) * 4 + a], sX[(kl * 64 + lane) * 4 + a]
     T *sYZ = (T *)lds_dyn, *sX = sYZ + 4 * qyz * 64;
     if (tlds) {
-      // table rows 0 .. 4 qyz - 1 are YZ_a[yz], the rest X_a[kx]; each wave
-      // issues SB row loads (clamped to a valid row) before it writes any of
-      // them to LDS, so their latencies overlap
+      // table rows 0 .. qyz - 1 are YZ[yz], the rest X[kx], four coefficients
+      // per cell each; each wave issues SB row loads (clamped to a valid row)
+      // before it writes any of them to LDS, so their latencies overlap
       constexpr int SB = 8;
-      const unsigned bj = (unsigned)min(c0 + lane, nx - 1) * (unsigned)sizeof(T);
-      const int nk = kx1 - kx0, nyz = 4 * qyz, nr = nyz + 4 * nk;
+      const unsigned bj = 4u * (unsigned)min(c0 + lane, nx - 1) * (unsigned)sizeof(T);
+      const int nk = kx1 - kx0, nr = qyz + nk;
       for (int base = wv; base < nr; base += SB * nwv) {
-        T v[SB];
+        T4 v[SB];
 #pragma unroll
         for (int u = 0; u < SB; u++) {
           const int rr = min(base + u * nwv, nr - 1);
-          const GAS T *src;
-          if (rr < nyz) {
-            const int a = rr / qyz, yz = rr - a * qyz;
-            src = tYZ + ((size_t)a * qyz + yz) * tstride;
-          } else {
-            const int q = rr - nyz, a = q / nk, k = q - a * nk;
-            src = tX + ((size_t)a * nkx + kx0 + k) * tstride;
-          }
-          v[u] = ldb(src, bj);
+          const GAS T *src = rr < qyz ? tYZ + (size_t)rr * tstride * 4 : tX + (size_t)(kx0 + rr - qyz) * tstride * 4;
+          v[u] = ldb((const GAS T4 *)src, bj);
         }
 #pragma unroll
         for (int u = 0; u < SB; u++) {
           const int rr = base + u * nwv;
-          if (rr < nyz) {
-            const int a = rr / qyz, yz = rr - a * qyz;
-            sYZ[(yz * 64 + lane) * 4 + a] = v[u];
-          } else if (rr < nr) {
-            const int q = rr - nyz, a = q / nk, k = q - a * nk;
-            sX[(k * 64 + lane) * 4 + a] = v[u];
-          }
+          if (rr < qyz) *(T4 *)(sYZ + (rr * 64 + lane) * 4) = v[u];
+          else if (rr < nr) *(T4 *)(sX + ((rr - qyz) * 64 + lane) * 4) = v[u];
         }
       }
       __syncthreads();
     }
     dxi = (T)invdx[jc];
     itau = invtau[jc];
-    const bool interior = tlds && c0 >= 3 && c0 + 66 <= nx;
+    const bool interior = c0 >= 3 && c0 + 66 <= nx;
     // interior tiles: per-wave LDS row buffers after the tables.  The row load
     // takes the tile's 64 aligned slots (cells c0 .. c0+62 and the padding
     // slot); a second load brings the halo: cells c0-3 .. c0-1 on lanes 0..2
     // and c0+63 .. c0+65 on lanes 3..5 (other lanes read past the row: zero)
-    T *sRow = sX + 4 * c_kxc * 64 + wv * 2 * ROWBUF;
+    T *sRow = (tlds ? sX + 4 * c_kxc * 64 : (T *)lds_dyn) + wv * 2 * ROWBUF;
     const unsigned oa = (unsigned)(64 * bm.y + lane) * (unsigned)sizeof(T);
     const unsigned oh = lane < 3 ? (unsigned)fslot(max(c0 - 3 + lane, 0)) * (unsigned)sizeof(T)
                                  : (lane < 6 ? (unsigned)fslot(min(c0 + 60 + lane, nx - 1)) * (unsigned)sizeof(T)
                                              : 0x80000000u);
     const CAS double *__restrict__ phi = (const CAS double *)(c.lat + lo_phi);
     const CAS double *__restrict__ bgc = (const CAS double *)(c.lat + lo_bg);
-    typedef T T4 __attribute__((ext_vector_type(4)));
+    const CAS double *__restrict__ xb = (const CAS double *)(c.lat + c.lo.xbg);
+    const CAS double *__restrict__ yzb = (const CAS double *)(c.lat + c.lo.yzbg);
     const unsigned rowbytes = (unsigned)c.nxp * (unsigned)sizeof(T);
+    // one buffer resource per population array over the chunk's rows: a row
+    // is a scalar byte offset, a cell the lane's offset (lanes past the
+    // chunk's range read zero and store nothing)
+    const size_t cbase = (size_t)kap_base * fstride;
+    const unsigned cbytes = (unsigned)(kx1 - kx0) * (unsigned)qyz * rowbytes;
+    const auto rs_in = rsrc_of(gin + cbase, cbytes);
+    const auto rs_fn = rsrc_of(fn + cbase, cbytes);
+    const auto rs_out = rsrc_of(out + cbase, cbytes);
     // global loads of a row (stencil of the stage input and f^n) are issued
     // two rows ahead; the tables (LDS, short latency) are read at the start of
     // the row's arithmetic
@@ -869,25 +913,25 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     auto rows = [&](auto posc, auto wallc, auto tlc, int ra, int rb) {
       constexpr bool POS = decltype(posc)::value, WALL = decltype(wallc)::value, TL = decltype(tlc)::value;
       if (ra >= rb) return;
-      const unsigned o0 = POS ? op0 : on0, o1 = POS ? op1 : on1, o2 = POS ? op2 : on2, o3 = POS ? op3 : on3,
-                     o4 = POS ? op4 : on4;
-      const bool g0 = POS ? gp0 : gn4, g1 = POS ? gp1 : gn3, g2 = POS ? gp2 : gn2;
-      const int mode = POS ? mode_p : mode_n;
+      Stencil st;
+      if (WALL) st = stencil(POS);
+      const unsigned o0 = st.o[0], o1 = st.o[1], o2 = st.o[2], o3 = st.o[3], o4 = st.o[4];
+      const bool g0 = st.g[0], g1 = st.g[1], g2 = st.g[2];
+      const int mode = st.mode;
       auto load = [&](int r, Row &d) {
-        const int kap = kap_base + r;
-        const auto rs = rsrc_of(gin + (size_t)kap * fstride, rowbytes);
+        const int so = (int)((unsigned)r * rowbytes);
         if (WALL) {
-          d.t0 = bld<T>(rs, o0); d.t1 = bld<T>(rs, o1); d.t2 = bld<T>(rs, o2); d.t3 = bld<T>(rs, o3);
-          d.t4 = bld<T>(rs, o4);
+          d.t0 = bld<T>(rs_in, o0, so); d.t1 = bld<T>(rs_in, o1, so); d.t2 = bld<T>(rs_in, o2, so);
+          d.t3 = bld<T>(rs_in, o3, so); d.t4 = bld<T>(rs_in, o4, so);
         } else {
-          d.t0 = bld<T>(rs, oa);
-          d.t1 = bld<T>(rs, oh);
+          d.t0 = bld<T>(rs_in, oa, so);
+          d.t1 = bld<T>(rs_in, oh, so);
         }
-        if (STAGE != 1) d.fnv = bld<T>(rsrc_of(fn + (size_t)kap * fstride, rowbytes), bcf);
+        if (STAGE != 1) d.fnv = bld<T>(rs_fn, bcf, so);
       };
       auto compute = [&](int r, const Row &d) {
         const int kap = kap_base + r;
-        const int kl = r / qyz, yz = r - kl * qyz;
+        const int kl = (int)__umulhi((unsigned)r, mq), yz = r - kl * qyz;
         const int kx = kx0 + kl;
         const CAS double *ph = phi + (size_t)kap * 8;
         const double pxd = ph[0];
@@ -898,10 +942,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
           y0 = yv.x; y1 = yv.y; y2 = yv.z; y3 = yv.w;
           x0 = xv.x; x1 = xv.y; x2 = xv.z; x3 = xv.w;
         } else {
-          const size_t ya = (size_t)qyz * tstride, xa = (size_t)nkx * tstride;
-          const GAS T *y = tYZ + (size_t)yz * tstride, *x = tX + (size_t)kx * tstride;
-          y0 = ldb(y, bc); y1 = ldb(y + ya, bc); y2 = ldb(y + 2 * ya, bc); y3 = ldb(y + 3 * ya, bc);
-          x0 = ldb(x, bc); x1 = ldb(x + xa, bc); x2 = ldb(x + 2 * xa, bc); x3 = ldb(x + 3 * xa, bc);
+          const T4 yv = ldb((const GAS T4 *)(tYZ + (size_t)yz * tstride * 4), 4 * bc);
+          const T4 xv = ldb((const GAS T4 *)(tX + (size_t)kx * tstride * 4), 4 * bc);
+          y0 = yv.x; y1 = yv.y; y2 = yv.z; y3 = yv.w;
+          x0 = xv.x; x1 = xv.y; x2 = xv.z; x3 = xv.w;
         }
         T v0, v1, v2, v3, v4, cen;
         T fh;
@@ -934,9 +978,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
           cen = POS ? v3 : v2;
           fh = weno_face_interior<T>(v0, v1, v2, v3, v4);
         }
-        const T fr = __shfl_down(fh, 1, 64);
+        const T fr = shift_down1(fh);
         T F = x0 * y0 + x1 * y1 + x2 * y2 + x3 * y3;
-        if (DF) F -= (T)bgc[kap];
+        // FP32: F - bg = dX0 dYZ0 + dX0 yzbg + xbg dYZ0 + sum_{a>0} X_a YZ_a, every
+        // term of the size of the deviation
+        if (DF) F += x0 * (T)yzb[yz] + (T)xb[kx] * y0;
         const T L = (-(T)pxd * dxi) * (fr - fh) + (F - cen) * itau;
         const T adv1 = cen + dt * L;
         T o;
@@ -944,7 +990,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
         else o = (STAGE == 2) ? (T)0.75 * d.fnv + (T)0.25 * adv1 : d.fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
         // lanes without a cell store past the row range (dropped), so the
         // store needs no branch
-        bst<T>(rsrc_of(out + (size_t)kap * fstride, rowbytes), is_cell ? bw : 0x80000000u, o);
+        bst<T>(rs_out, is_cell ? bw : 0x80000000u, (int)((unsigned)r * rowbytes), o);
         // lanes that own no cell accumulate values that are never stored
         const double od = (double)o;
         acc[0] += od;
@@ -981,9 +1027,12 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
     };
     using TT = BoolC<true>;
     using FF = BoolC<false>;
-    if (interior) {
+    if (interior && tlds) {
       rows(TT(), FF(), TT(), r0, min(r1, rsplit));
       rows(FF(), FF(), TT(), max(r0, rsplit), r1);
+    } else if (interior) {
+      rows(TT(), FF(), FF(), r0, min(r1, rsplit));
+      rows(FF(), FF(), FF(), max(r0, rsplit), r1);
     } else if (tlds) {
       rows(TT(), TT(), TT(), r0, min(r1, rsplit));
       rows(FF(), TT(), TT(), max(r0, rsplit), r1);
@@ -991,7 +1040,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       rows(TT(), TT(), FF(), r0, min(r1, rsplit));
       rows(FF(), TT(), FF(), max(r0, rsplit), r1);
     }
-    if (tlds) __syncthreads();   // the tables' LDS is reused by the partial sums
+    // the LDS of the tables and row buffers is reused by the partial sums
+    if (tlds || interior) __syncthreads();
   } else {
     // body force couples the velocities of one y-line: a wave takes whole lines
     const T ay = (T)c.ay;
@@ -1000,35 +1050,37 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FDLB_U
       const int kx = kx0 + line / qz, kz = line - (line / qz) * qz;
       const double pxd = lat[lo_px + kx];
       const bool pos = kx < c_qh;               // positive x nodes come first
-      const size_t xa = (size_t)nkx * tstride;
-      const GAS T *xr = tX + (size_t)kx * tstride;
-      const T X0 = ldb(xr, bc), X1 = ldb(xr + xa, bc), X2 = ldb(xr + 2 * xa, bc), X3 = ldb(xr + 3 * xa, bc);
+      const Stencil st = stencil(pos);
+      const T4 xv = ldb((const GAS T4 *)(tX + (size_t)kx * tstride * 4), 4 * bc);
+      const T X0 = xv.x, X1 = xv.y, X2 = xv.z, X3 = xv.w;
       const GAS T *gw = pos ? gwL : gwR;
       const double nw = pos ? nwl : nwr;
-      T cen[MAXQY], adv[MAXQY];
+      // every global read of the line (stencils, targets, f^n) comes before
+      // its first store, so their latencies overlap
+      T cen[MAXQY], adv[MAXQY], tgt[MAXQY], fnv[MAXQY];
 #pragma unroll
       for (int ky = 0; ky < MAXQY; ky++) {
         if (ky < qy) {
           const int kap = (kx * qy + ky) * qz + kz;
           const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
-          const T fh = face(gin + (size_t)kap * fstride, pos, fw, cen[ky]);
-          const T fr = __shfl_down(fh, 1, 64);
+          const T fh = face(gin + (size_t)kap * fstride, st, pos, fw, cen[ky]);
+          const T fr = shift_down1(fh);
           adv[ky] = -(T)pxd * dxi * (fr - fh);
+          tgt[ky] = target(kx, ky * qz + kz, X0, X1, X2, X3);
+          fnv[ky] = STAGE == 1 ? (T)0 : ldb(fn + (size_t)kap * fstride, bcf);
         }
       }
 #pragma unroll
       for (int ky = 0; ky < MAXQY; ky++) {
         if (ky < qy) {
           const int kap = (kx * qy + ky) * qz + kz;
-          const int yz = ky * qz + kz;
           T sf = 0;
           const GAS double *km = lat + c.lo.kmat + ky * qy;
 #pragma unroll
           for (int k2 = 0; k2 < MAXQY; k2++)
             if (k2 < qy) sf += (T)km[k2] * cen[k2];
-          T F = target(yz, X0, X1, X2, X3);
-          if (DF) { sf += (T)lat[c.lo.kbg + kap]; F -= (T)lat[c.lo.bg + kap]; }
-          finish(kap, ky, kz, pxd, cen[ky], adv[ky] - ay * sf + (F - cen[ky]) * itau);
+          if (DF) sf += (T)lat[c.lo.kbg + kap];
+          finish(kap, ky, kz, pxd, cen[ky], adv[ky] - ay * sf + (tgt[ky] - cen[ky]) * itau, fnv[ky]);
         }
       }
     }
@@ -1061,11 +1113,17 @@ __global__ void __launch_bounds__(512) k_fill(const CaseDev *__restrict__ cases,
   for (int r = wv; r < nrows; r += nwv) {
     const int kx = kx0 + r / qyz, yz = r % qyz, ky = yz / qz, kz = yz % qz;
     const int kap = kx * qyz + yz;
+    const T *xr = tX + ((size_t)kx * nx + jc) * 4, *yr = tYZ + ((size_t)yz * nx + jc) * 4;
     double F = 0;
-    for (int a = 0; a < 4; a++)
-      F += (double)tX[(size_t)(a * nkx + kx) * nx + jc] * (double)tYZ[(size_t)(a * qyz + yz) * nx + jc];
-    if (use_noise) F *= 1.0 + c.noise[(size_t)kap * nx + jc];
-    if (sizeof(T) == 4) F -= lat[c.lo.bg + kap];   // FP32 storage: deviation from the background
+    for (int a = 0; a < 4; a++) F += (double)xr[a] * (double)yr[a];
+    if (sizeof(T) == 4) {
+      // FP32 storage: the tables give the deviation from the background
+      // (F - bg = dX0 dYZ0 + dX0 yzbg + xbg dYZ0 + sum_{a>0} X_a YZ_a)
+      F += (double)xr[0] * lat[c.lo.yzbg + yz] + lat[c.lo.xbg + kx] * (double)yr[0];
+      if (use_noise) F += (F + lat[c.lo.bg + kap]) * c.noise[(size_t)kap * nx + jc];
+    } else if (use_noise) {
+      F *= 1.0 + c.noise[(size_t)kap * nx + jc];
+    }
     const T o = (T)F;
     if (is_cell) {
       f[(size_t)kap * c.nxp + fslot(j)] = o;
@@ -1210,7 +1268,7 @@ static void upd(int stage, dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t
 
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds) {
   const size_t part = (size_t)waves * NRAW * 64 * sizeof(double);
-  const size_t tab = tlds ? ((size_t)4 * (qyz + kxc) * 64 + (size_t)waves * 2 * ROWBUF) * (prec == 0 ? 8 : 4) : 0;
+  const size_t tab = ((tlds ? (size_t)4 * (qyz + kxc) * 64 : 0) + (size_t)waves * 2 * ROWBUF) * (prec == 0 ? 8 : 4);
   return part > tab ? part : tab;
 }
 

@@ -221,6 +221,8 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   o.bg = off; off += c.K;
   o.kbg = off; off += c.K;
   o.bgm = off; off += NRAW;
+  o.xbg = off; off += 2 * Q;
+  o.yzbg = off; off += c.qy * c.qz;
   o.total = off;
   c.lat.assign(off, 0.0);
   double *L = c.lat.data();
@@ -369,11 +371,14 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     host_full_table(&L[o.Hy], c.qy, p.uy_init, p.t_init, 0, Y.data());
     host_full_table(&L[o.Hz], c.qz, 0.0, p.t_init, 0, Z.data());
     for (int m = 0; m < NRAW; m++) L[o.bgm + m] = 0;
+    for (int kx = 0; kx < 2 * Q; kx++) L[o.xbg + kx] = p.n_init * X[kx];
+    for (int ky = 0; ky < c.qy; ky++)
+      for (int kz = 0; kz < c.qz; kz++) L[o.yzbg + ky * c.qz + kz] = Y[ky] * Z[kz];
     for (int kx = 0; kx < 2 * Q; kx++)
       for (int ky = 0; ky < c.qy; ky++)
         for (int kz = 0; kz < c.qz; kz++) {
           const int kap = (kx * c.qy + ky) * c.qz + kz;
-          const double b = p.n_init * X[kx] * Y[ky] * Z[kz];
+          const double b = L[o.xbg + kx] * L[o.yzbg + ky * c.qz + kz];
           L[o.bg + kap] = b;
           L[o.bgm] += b;
           for (int m = 1; m < NRAW; m++) L[o.bgm + m] += L[o.phi + kap * 8 + m - 1] * b;

@@ -43,30 +43,43 @@ def test_gemm_bf16_layout_and_values(M, N, K, ta, tb):
     assert np.max(np.abs(got - ref)) < 1e-5 * (1 + np.max(np.abs(ref)))
 
 
-def test_gradient_matches_cpu_reference():
+@pytest.mark.parametrize("width,depth,n_out,batch", [(256, 4, 640, 256), (64, 3, 40, 50)])
+def test_gradient_matches_cpu_reference_elementwise(width, depth, n_out, batch):
+    """Every weight and bias gradient element against the FP64 reference that
+    rounds the same operands to BF16 as the GPU (input, weights, hidden
+    activations, back-propagated errors; oracle/mlp_ref.loss_grad_bf16).  The
+    first case is the warm-start network itself (10 -> 4 x 256 GELU -> 640).
+    What is left is FP32 accumulation order and the BF16 roundings it flips
+    (an FP32 emulation of the same network on the CPU differs from the FP64
+    one by at most 1.1e-3 of a tensor's largest element, with median relative
+    error 3e-4 and 99th percentile 2e-2); a dropped term, a wrong scale or a
+    transposed operand moves whole tensors."""
     from paper_2308_15407_amd.mlp import WarmStartNet, layer_shapes
-    net = WarmStartNet(n_in=10, width=64, depth=3, n_out=40, max_batch=64, seed=3)
+    net = WarmStartNet(n_in=10, width=width, depth=depth, n_out=n_out, max_batch=batch, seed=3)
     rng = np.random.default_rng(1)
-    x = rng.normal(size=(50, 10)).astype(np.float32)
-    t = rng.normal(size=(50, 40)).astype(np.float32)
+    x = rng.normal(size=(batch, 10)).astype(np.float32)
+    t = rng.normal(size=(batch, n_out)).astype(np.float32)
     loss, g = net.loss_grad(x, t)
     p = net.get_params().astype(np.float64)
-    shapes = layer_shapes(10, 64, 3, 40)
-    # the GPU multiplies BF16-rounded weights and inputs
-    pr = p.copy()
+    shapes = layer_shapes(10, width, depth, n_out)
+    Lr, gr = R.loss_grad_bf16(p, shapes, x.astype(np.float64), t.astype(np.float64))
+    print("loss gpu %.7f ref %.7f" % (loss, Lr), flush=True)
+    assert abs(loss - Lr) < 1e-4 * abs(Lr)
     off = 0
-    for fin, fout in shapes:
-        pr[off:off + fin * fout] = bf16_round(p[off:off + fin * fout]); off += fin * fout + fout
-    Lr, gr = R.loss_grad(pr, shapes, bf16_round(x), t)
-    print("loss gpu %.6f ref %.6f; grad rel err %.3e" % (loss, Lr, np.linalg.norm(g - gr) / np.linalg.norm(gr)))
-    assert abs(loss - Lr) < 2e-2 * abs(Lr)
-    assert np.linalg.norm(g - gr) < 3e-2 * np.linalg.norm(gr)
-    off = 0
-    for fin, fout in shapes:   # every layer's gradient points the same way
-        n = fin * fout + fout
-        a, b = g[off:off + n], gr[off:off + n]
-        assert np.dot(a, b) > 0.995 * np.linalg.norm(a) * np.linalg.norm(b)
-        off += n
+    for layer, (fin, fout) in enumerate(shapes):
+        for name, n in (("W", fin * fout), ("b", fout)):
+            a_, b_ = g[off:off + n].astype(np.float64), gr[off:off + n]
+            off += n
+            scale = np.max(np.abs(b_))
+            err = np.abs(a_ - b_)
+            rel = err / (np.abs(b_) + 1e-3 * scale)
+            print("layer %d %s (%d): max |dg| %.1e of max |g|, relative: median %.1e, 99th percentile %.1e" %
+                  (layer, name, n, err.max() / scale, np.median(rel), np.percentile(rel, 99)), flush=True)
+            assert scale > 0
+            assert err.max() < 5e-3 * scale, (layer, name)
+            assert np.median(rel) < 1e-3, (layer, name)
+            assert np.percentile(rel, 99) < 5e-2, (layer, name)
+    assert off == g.size
 
 
 def test_training_reduces_loss():

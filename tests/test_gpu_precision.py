@@ -1,19 +1,15 @@
 """FP32-bulk storage with FP64 moments, wall balance and residual, against
-the FP64 oracle.  Per-moment bounds (n, T pointwise relative; u, q, P_xy
-relative to their channel maximum): 1e-5 for n, u_y, T and P_xy; 1e-4 for
-u_x and q_x, which are small in these flows so that the FP32 rounding of the
-populations (~6e-8 of f, summed with weights |p|^3 up to p ~ 8) is amplified
-by 1/max|u_x| and 1/max|q_x|."""
+the FP64 oracle: every moment (n, u, T, q, the stresses) within 1e-5, with n,
+T and the normal stresses relative pointwise and u, q, P_xy relative to their
+channel maximum."""
 import numpy as np
 import pytest
 
 import fdlb_inputs as I
 from oracle import oracle as O
-from tests.gpu_util import rel_moment_errors, seeded_state
+from tests.gpu_util import assert_fp32_moments, rel_moment_errors, seeded_state
 
 pytestmark = pytest.mark.gpu
-
-TOL32 = 1e-5
 
 
 def _run_pair(cfg, steps, seed):
@@ -28,34 +24,36 @@ def _run_pair(cfg, steps, seed):
     return s, o
 
 
-# C2 at full size and C3 at Nx = 160 include interior update tiles (no wall in the stencil)
-@pytest.mark.parametrize("name,over,steps", [("C1", {}, 200), ("C2", {}, 100),
+# C2 and C3 at full size (Nx = 256, K = 256; Nx = 512, K = 768) include interior
+# update tiles (no wall in the stencil) and, for C3, the body-force path
+@pytest.mark.parametrize("name,over,steps", [("C1", {}, 200), ("C2", {}, 100), ("C3", {}, 30),
                                              ("C3", dict(nx=160, qx_half=6), 60)])
 def test_fp32_bulk_moment_errors(name, over, steps):
     cfg = I.config(name, **over)
     s, o = _run_pair(cfg, steps, 40)
-    err = rel_moment_errors(s.moments(0), o.moments())
-    print("FP32 bulk %s %d steps:" % (name, steps), {k: "%.1e" % v for k, v in err.items()}, flush=True)
-    for k in ("n", "uy", "T", "Pxy"):
-        assert err[k] < TOL32, (k, err[k])
-    for k in ("ux", "qx"):
-        assert err[k] < 10 * TOL32, (k, err[k])
+    assert_fp32_moments(s.moments(0), o.moments(), "%s nx=%d K=%d, %d steps" % (name, cfg["nx"], o.K, steps))
 
 
 def test_fp32_run_to_steady_then_fp64_finish():
-    """FP32 bulk converges (deviation storage reaches a fixed point of the
-    FP32 map), and an explicit promotion finishes on the FP64 steady state."""
+    """FP32 bulk runs to the steady state: either the FP32 map settles below
+    the tolerance by itself, or its residual stalls at the rounding level of
+    the stored deviations and the stall rule promotes the case to FP64, which
+    finishes.  Either way the steady moments are within 1e-5 of the oracle's,
+    and an explicit promotion (a no-op after a stall promotion) then converges
+    on the FP64 steady state."""
     from paper_2308_15407_amd.solver import Solver
     cfg = I.config("C1", nx=24)
     o = O.Oracle(**cfg)
     o.run_to_steady(1e-12, 400000)
     s = Solver(dict(cfg, precision=1))
-    st, res, code = s.run_to_steady(tol=1e-8, max_steps=200000, check_every=50)
-    assert code == 0 and res[0] < 1e-8 and s.precision(0) == 1
-    err32 = rel_moment_errors(s.moments(0), o.moments())
-    print("FP32 steady:", {k: "%.1e" % v for k, v in err32.items()}, flush=True)
-    for k in ("n", "T"):
-        assert err32[k] < 1e-5, (k, err32[k])
+    # tol 1e-9: below the FP32 map's own rounding floor, so the case stalls and
+    # finishes in FP64; u_x (5e-5 at most, in the wall cells) then differs from
+    # the oracle's r < 1e-12 state by the residual's remainder, not by 1e-9 / dt
+    st, res, code = s.run_to_steady(tol=1e-9, max_steps=200000, check_every=50)
+    print("FP32 run to steady: %d steps, residual %.1e, final storage %s" %
+          (st[0], res[0], "FP32" if s.precision(0) == 1 else "FP64 (promoted on stall)"), flush=True)
+    assert code == 0 and res[0] < 1e-9
+    assert_fp32_moments(s.moments(0), o.moments(), "C1 nx=24 steady")
     # FP32 rounding of the stored deviations does not conserve mass exactly
     x, jac = s.grid(0)
     deta = 2.0 / cfg["nx"]

@@ -10,7 +10,7 @@ import numpy as np
 import pytest
 
 import fdlb_inputs as I
-from tests.gpu_util import rel_moment_errors, seeded_state
+from tests.gpu_util import assert_fp32_moments, rel_moment_errors, seeded_state
 from tests.test_gpu_parity import TOL64, _compare, _pair
 
 pytestmark = pytest.mark.gpu
@@ -33,12 +33,7 @@ def test_wide_orders_match_oracle(flow, kw, prec):
     if prec == 0:
         _compare(s, o, TOL64, "%s Q=%d" % (flow, kw["qx_half"]))
     else:
-        err = rel_moment_errors(s.moments(0), o.moments())
-        print("%s Q=%d FP32" % (flow, kw["qx_half"]), {k: "%.1e" % v for k, v in err.items()}, flush=True)
-        for k in ("n", "uy", "T", "Pxy"):
-            assert err[k] < 1e-5, (k, err[k])
-        for k in ("ux", "qx"):
-            assert err[k] < 1e-4, (k, err[k])
+        assert_fp32_moments(s.moments(0), o.moments(), "%s Q=%d" % (flow, kw["qx_half"]))
 
 
 @pytest.mark.parametrize("Q", [64, 120, 200])
