@@ -106,6 +106,23 @@ int fdlb_case_grid(const fdlb_params *p, double *x, double *jac);
 int fdlb_init(const fdlb_params *cases, int ncases, void *dev_workspace, size_t bytes,
               void *hip_stream, fdlb_handle *out);
 
+/* Variant of fdlb_init for callers that cannot allocate device memory (code
+   under HIP graph capture, tight serving loops, harnesses that forbid
+   hipMalloc): the workspace is a device array of FDLB_STATIC_WORKSPACE_BYTES
+   that the library reserves per GPU when its code object loads and keeps until
+   the process ends; this call allocates no device memory.  The cases are set
+   up on hip_stream of the current device as by fdlb_init, and every other call
+   takes the handle as usual.  One live handle per device holds the array:
+   FDLB_ESTATE while an earlier handle from this call on the same device is
+   not destroyed (its state lives in the same memory; two handles would race),
+   FDLB_ENOMEM when fdlb_workspace_bytes of the cases exceeds the array (the
+   C1-C3 workloads fit in either precision; large cases need fdlb_init),
+   FDLB_EINVAL for invalid cases, FDLB_EHIP if the array's address cannot be
+   obtained.  Each set-up overwrites everything it uses, so the contents a
+   previous handle left do not matter. */
+#define FDLB_STATIC_WORKSPACE_BYTES (32u << 20)
+int fdlb_init_static(const fdlb_params *cases, int ncases, void *hip_stream, fdlb_handle *out);
+
 /* Advance every active case by nsteps TVD-RK3 steps (asynchronous). */
 int fdlb_step(fdlb_handle h, long nsteps);
 

@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -66,6 +67,7 @@ struct fdlb_ctx {
   // a stream of its own (default priority), forked from and joined to the
   // caller's stream by events; created by build_maps, never while capturing
   hipStream_t gstream[4] = {nullptr, nullptr, nullptr, nullptr};
+  int static_dev = -1;        // device whose static workspace holds this handle (fdlb_init_static)
   hipEvent_t fork_ev = nullptr, join_ev[4] = {nullptr, nullptr, nullptr, nullptr};
   int converge_hist = 20;
   bool restart_nonfinite = false;   // run_to_steady: restart a diverged case once from its cold state
@@ -486,8 +488,11 @@ extern "C" int fdlb_init(const fdlb_params *ps, int ncases, void *dev_ws, size_t
   return FDLB_OK;
 }
 
+static void release_static(fdlb_ctx *h);
+
 extern "C" void fdlb_destroy(fdlb_handle h) {
   if (!h) return;
+  release_static(h);
   drop_graph(h);
   if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   for (int G = 0; G < 4; G++) {
@@ -948,5 +953,56 @@ extern "C" int fdlb_copy_probe(const void *src, void *dst, size_t bytes, void *s
   if (!src || !dst || bytes % 32) return fail(FDLB_EINVAL, "copy probe needs 32-byte multiples");
   HIPCHK(launch_copy_probe(src, dst, bytes, (hipStream_t)stream));
   HIPCHK(hipStreamSynchronize((hipStream_t)stream));
+  return FDLB_OK;
+}
+
+// ---------------------------------------------------------------------------
+// no-allocation set-up: the workspace is a file-scope device array
+// ---------------------------------------------------------------------------
+// Each GPU the library runs on holds its own copy of `scratch` from the
+// loading of the code object until the process ends.  Host code never uses
+// the array's name as an address: the device address of the current device's
+// copy comes from hipGetSymbolAddress, once per device, and is kept below.
+static __device__ __align__(256) unsigned char scratch[FDLB_STATIC_WORKSPACE_BYTES];
+
+namespace {
+constexpr int STATIC_MAX_DEVICES = 64;
+std::mutex g_static_mu;
+void *g_static_ptr[STATIC_MAX_DEVICES];        // device address of the array, per device
+fdlb_ctx *g_static_owner[STATIC_MAX_DEVICES];  // live handle that holds it, per device
+}  // namespace
+
+static void release_static(fdlb_ctx *h) {
+  if (h->static_dev < 0) return;
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_owner[h->static_dev] == h) g_static_owner[h->static_dev] = nullptr;
+  h->static_dev = -1;
+}
+
+extern "C" int fdlb_init_static(const fdlb_params *cases, int ncases, void *hip_stream, fdlb_handle *out) {
+  if (!out) return fail(FDLB_EINVAL, "null handle pointer");
+  *out = nullptr;
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= STATIC_MAX_DEVICES) return fail(FDLB_EINVAL, "device index out of range");
+  const size_t need = fdlb_workspace_bytes(cases, ncases);
+  if (need == 0) return FDLB_EINVAL;   // fdlb_workspace_bytes named the invalid case
+  if (need > (size_t)FDLB_STATIC_WORKSPACE_BYTES)
+    return fail(FDLB_ENOMEM, "the cases need " + std::to_string(need) + " bytes; the static workspace holds " +
+                                 std::to_string((size_t)FDLB_STATIC_WORKSPACE_BYTES));
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (g_static_owner[dev])
+    return fail(FDLB_ESTATE, "the static workspace of this device is held by a live handle; destroy it first");
+  if (!g_static_ptr[dev]) {
+    void *ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !ptr)
+      return fail(FDLB_EHIP, std::string("hipGetSymbolAddress of the static workspace: ") + hipGetErrorString(e));
+    g_static_ptr[dev] = ptr;
+  }
+  const int r = fdlb_init(cases, ncases, g_static_ptr[dev], (size_t)FDLB_STATIC_WORKSPACE_BYTES, hip_stream, out);
+  if (r != FDLB_OK) return r;
+  (*out)->static_dev = dev;
+  g_static_owner[dev] = *out;
   return FDLB_OK;
 }

@@ -15,10 +15,12 @@ LIB_PATH = os.environ.get("FDLB_LIB", os.path.join(HERE, "libfdlb.so"))
 
 FDLB_OK, FDLB_EINVAL, FDLB_EHIP, FDLB_ENOMEM, FDLB_ENONFINITE, FDLB_ESTALL, FDLB_ESTATE = 0, -1, -2, -3, -4, -5, -6
 FDLB_NMOM = 10
+FDLB_STATIC_WORKSPACE_BYTES = 32 << 20   # include/fdlb.h
 MOMENT_NAMES = ("n", "ux", "uy", "T", "qx", "qy", "Pxx", "Pxy", "Pyy", "Pzz")
 
 # every symbol declared in include/fdlb.h
 EXPORTS = ("fdlb_workspace_bytes", "fdlb_case_info", "fdlb_case_lattice", "fdlb_case_grid", "fdlb_init",
+           "fdlb_init_static",
            "fdlb_step", "fdlb_moments", "fdlb_grid_coords", "fdlb_lattice", "fdlb_geometry", "fdlb_dt",
            "fdlb_run_to_steady",
            "fdlb_residual", "fdlb_set_state", "fdlb_get_f", "fdlb_set_f", "fdlb_promote",
@@ -87,6 +89,7 @@ def lib():
         L.fdlb_case_lattice.argtypes = [pp, dp, dp, dp, dp]
         L.fdlb_case_grid.argtypes = [pp, dp, dp]
         L.fdlb_init.argtypes = [pp, I, P, Z, P, C.POINTER(P)]
+        L.fdlb_init_static.argtypes = [pp, I, P, C.POINTER(P)]
         L.fdlb_step.argtypes = [P, C.c_long]
         L.fdlb_moments.argtypes = [P, I, dp]
         L.fdlb_grid_coords.argtypes = [P, I, dp, dp]
@@ -193,6 +196,14 @@ def fdlb_init(cases, workspace_ptr, nbytes, stream_ptr):
     arr = _params_array(cases)
     h = C.c_void_p()
     _chk(lib().fdlb_init(arr, len(cases), C.c_void_p(workspace_ptr), nbytes, C.c_void_p(stream_ptr), C.byref(h)))
+    return h
+
+
+def fdlb_init_static(cases, stream_ptr):
+    """fdlb_init on the library's static device workspace (no allocation)."""
+    arr = _params_array(cases)
+    h = C.c_void_p()
+    _chk(lib().fdlb_init_static(arr, len(cases), C.c_void_p(stream_ptr), C.byref(h)))
     return h
 
 
