@@ -123,10 +123,15 @@ class FeatureScaler:
 def study_params(draw, nx=64, qx_max=8):
     """Case of the learned-warm-start study from one sweep draw: the draw's
     flow, Kn, eta0 and wall/force data on an nx-cell uniform grid with the
-    draw's half-range order capped at qx_max, Q_y = Q_z = 4."""
+    draw's half-range order capped at qx_max, Q_y = Q_z = 4.  nx = 0 keeps the
+    sweep generator's own grid (Nx 64-512, tanh-stretched from 256 cells) and
+    qx_max = 0 its half-range order (4-16): the full generator."""
     import fdlb_inputs as I
     d = I.c4_params(draw)
-    d.update(nx=nx, grid=0, stretch=0.0, qx_half=min(draw["qx_half"], qx_max))
+    if nx:
+        d.update(nx=nx, grid=0, stretch=0.0)
+    if qx_max:
+        d.update(qx_half=min(draw["qx_half"], qx_max))
     return d
 
 

@@ -8,6 +8,8 @@ evaluation of time to steady state).
 Cases come from the sweep generator (flow, Kn, eta0, wall data, force) on a
 64-cell uniform grid with Q_x^h <= 8 and Q_y = Q_z = 4; draws with R < 2 or
 Kn < 0.05 are rejected.  Training seeds start at 1, held-out seeds at 100001.
+--nx 0 --qx-max 0 keeps the generator's own grids and orders (Nx 64-512,
+Q_x^h 4-16); --kn-min 0.01 its whole Knudsen range.
 """
 import argparse
 import json
@@ -59,7 +61,10 @@ def cmd_eval(args):
     from . import learned as LW
     model = LW.WarmStartModel.load(args.weights)
     held = LW.draw_cases(100001, args.count, kn_min=args.kn_min, nx=args.nx, qx_max=args.qx_max)
-    out = {"n_drawn": len(held), "tol": args.tol, "max_steps": args.max_steps}
+    out = {"n_drawn": len(held), "tol": args.tol, "max_steps": args.max_steps, "kn_min": args.kn_min,
+           "generator": "sweep generator, %s, %s, Kn >= %g, R >= 2" % (
+               "its own grids (Nx 64-512)" if not args.nx else "Nx = %d uniform" % args.nx,
+               "Q_x^h 4-16" if not args.qx_max else "Q_x^h <= %d" % args.qx_max, args.kn_min)}
     moms, grids, st, res, wall = LW.solve_steady(held, args.tol, args.max_steps, check_every=args.check, precision=0)
     ok = [i for i in range(len(held)) if res[i] < args.tol]
     out["not_converged_plain_seeds"] = [held[i]["_seed"] for i in range(len(held)) if not (res[i] < args.tol)]
@@ -87,6 +92,8 @@ def cmd_eval(args):
     arms = (("batched_fp64_cold", 0, None), ("batched_fp32_cold", 1, None),
             ("batched_fp32_learned", 1, True), ("batched_fp64_learned", 0, True),
             ("batched_fp32_learned_maxwellian", 1, False), ("batched_fp64_learned_maxwellian", 0, False))
+    if args.short:
+        arms = arms[:4]
     for name, prec, g13 in arms:
         nfb = 0
         if g13 is not None:
@@ -105,7 +112,7 @@ def cmd_eval(args):
             % (name, wall, wall / len(cases), np.mean(st), np.median(st), np.max(st), runs[name]["converged"],
                len(cases), nfb))
     for p in ("fp32", "fp64"):
-        for v in ("", "_maxwellian"):
+        for v in ("", "_maxwellian") if not args.short else ("",):
             r = steps["batched_%s_learned%s" % (p, v)] / np.maximum(steps["batched_%s_cold" % p], 1)
             runs["step_ratio_learned%s_over_cold_%s" % (v, p)] = {"mean": float(np.mean(r)),
                                                                    "median": float(np.median(r))}
@@ -151,6 +158,7 @@ def main(argv=None):
             p.add_argument("--count", type=int, default=512)
             p.add_argument("--seq-count", type=int, default=24)
             p.add_argument("--check", type=int, default=100)
+            p.add_argument("--short", action="store_true", help="only the Grad-13 learned and cold arms")
     args = ap.parse_args(argv)
     {"data": cmd_data, "train": cmd_train, "eval": cmd_eval}[args.cmd](args)
 
