@@ -25,7 +25,7 @@ GRID_UNIFORM, GRID_TANH = 0, 1
 BASE = dict(flow=FOURIER, kn=0.1, eta0=0.05, t_left=1.0, t_right=1.0, uy_left=0.0, uy_right=0.0,
             ay=0.0, n_init=1.0, t_init=1.0, uy_init=0.0, nx=64, grid=GRID_UNIFORM, stretch=0.0,
             qx_half=4, qy=3, qz=3, collision=BGK, pr_fixed=2.0 / 3.0, chi_mode=0, j1_shear=1,
-            cfl=0.5, dt=0.0)
+            cfl=0.5, dt=0.0, x_rule=0)
 
 
 def config(name, **over):

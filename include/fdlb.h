@@ -51,6 +51,7 @@ enum fdlb_flow { FDLB_FOURIER = 0, FDLB_COUETTE = 1, FDLB_POISEUILLE = 2 };
 enum fdlb_collision { FDLB_BGK = 0, FDLB_SHAKHOV_FIXED_PR = 1, FDLB_SHAKHOV_DENSE_PR = 2 };
 enum fdlb_grid { FDLB_GRID_UNIFORM = 0, FDLB_GRID_TANH = 1 };
 enum fdlb_precision { FDLB_F64 = 0, FDLB_F32_BULK = 1 };
+enum fdlb_x_rule { FDLB_X_HALF_RANGE = 0, FDLB_X_FULL_RANGE = 1 };
 
 /* Problem statement of one channel case (Sec. II.A, Sec. IV, Table tab:quad). */
 typedef struct {
@@ -76,6 +77,13 @@ typedef struct {
   int j1_shear;              /* 1: keep the xi_x xi_y du_y/dx term of J1 (3D operator) */
   double cfl, dt;            /* dt > 0 overrides dt = cfl * min cell / max |p_x| */
   int precision;             /* fdlb_precision */
+  int x_rule;                /* fdlb_x_rule: FDLB_X_HALF_RANGE (0, the method, Sec. III.A.2) or
+                                FDLB_X_FULL_RANGE (1): a full-range Gauss-Hermite rule of order
+                                2*qx_half on x, the comparison of App. A (fig:full_vs_half);
+                                2*qx_half <= 200; the lattice keeps the same layout (kx <
+                                qx_half are the positive nodes, kx >= qx_half their mirror
+                                images) and the projections are the full-range ones
+                                (eq:g_H, eq:H_gk); not available for the reduced models */
 } fdlb_params;
 
 typedef struct fdlb_ctx *fdlb_handle;

@@ -34,7 +34,7 @@ class OrcParams(C.Structure):
                 ("qx_half", C.c_int), ("qy", C.c_int), ("qz", C.c_int),
                 ("collision", C.c_int), ("pr_fixed", C.c_double),
                 ("chi_mode", C.c_int), ("j1_shear", C.c_int),
-                ("cfl", C.c_double), ("dt", C.c_double)]
+                ("cfl", C.c_double), ("dt", C.c_double), ("x_rule", C.c_int)]
 
 
 _lib = None
@@ -71,6 +71,10 @@ def lib():
         L.orc_face_fluxes.argtypes = [P, dp, dp, dp]
         L.orc_gh_rule.restype = I
         L.orc_gh_rule.argtypes = [I, dp, dp]
+        L.orc_gh_rule_n.restype = I
+        L.orc_gh_rule_n.argtypes = [I, dp, dp]
+        L.orc_project_fullx_table.restype = I
+        L.orc_project_fullx_table.argtypes = [I, D, D, I, dp]
         L.orc_hr_rule.restype = I
         L.orc_hr_rule.argtypes = [I, dp, dp, P]
         L.orc_project_half_table.restype = I
@@ -104,7 +108,7 @@ def lib():
 DEFAULTS = dict(flow=0, kn=0.1, eta0=0.05, t_left=1.0, t_right=1.0, uy_left=0.0, uy_right=0.0,
                 ay=0.0, n_init=1.0, t_init=1.0, uy_init=0.0, nx=64, grid=0, stretch=0.0,
                 qx_half=4, qy=3, qz=3, collision=0, pr_fixed=2.0 / 3.0, chi_mode=0, j1_shear=1,
-                cfl=0.5, dt=0.0)
+                cfl=0.5, dt=0.0, x_rule=0)
 
 
 class Oracle:
@@ -240,6 +244,24 @@ def gh_rule(Q):
     if lib().orc_gh_rule(Q, n, w):
         raise RuntimeError("gh rule failed")
     return n, w
+
+
+def gh_rule_n(Q):
+    """Full-range rule of order Q <= 96 from the scaled Hermite recurrence
+    (the x rule of x_rule = 1)."""
+    n, w = np.zeros(Q), np.zeros(Q)
+    if lib().orc_gh_rule_n(Q, n, w):
+        raise RuntimeError("gh rule failed")
+    return n, w
+
+
+def project_fullx(qh, u, T, a):
+    """Full-range x projection of g (p-u)^a at the 2 qh nodes of an x_rule = 1
+    lattice (positive nodes first, then their mirror images)."""
+    out = np.zeros(2 * qh)
+    if lib().orc_project_fullx_table(qh, u, T, a, out):
+        raise RuntimeError("projection failed")
+    return out
 
 
 def hr_rule(Q):

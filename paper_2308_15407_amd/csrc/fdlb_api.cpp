@@ -58,7 +58,7 @@ struct fdlb_ctx {
   int waves = 4;
   int kx_user = 0;
   int tileT[4] = {CTILE, CTILE, CTILE, CTILE};   // cells per block of each group's table map
-  bool wideT[4] = {false, false, false, false};  // the group holds cases with qx_half > MAXQH
+  bool wideT[4] = {false, false, false, false};  // the group holds cases of the wide table pass
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -207,7 +207,7 @@ static int build_maps(fdlb_ctx *h) {
       if (!c.active) continue;
       const int P = c.prec * 2 + (c.p.ay != 0.0 ? 1 : 0);
       blocks[P] += (c.nx + CTILE - 1) / CTILE + 2;
-      gwide[P] = gwide[P] || c.qh > MAXQH;
+      gwide[P] = gwide[P] || c.wide;
     }
     for (int G = 0; G < 4; G++) {
       h->wideT[G] = gwide[G];
@@ -393,9 +393,9 @@ static int set_state_dev(fdlb_ctx *h, int ci, const double *fields, const double
   int *tmp = h->d_map + 4 * (h->map_cap - (mt.size() + mu.size()) / 4);
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, c.qh > MAXQH, CTILE, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_FIELDS | TM_TABLES, 0, c.wide, CTILE, h->stream));
   HIPCHK(launch_fill(P, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, noise ? 1 : 0, h->stream));
-  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, c.qh > MAXQH, CTILE, h->stream));
+  HIPCHK(launch_table(P, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, c.wide, CTILE, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   c.steps = 0;
   c.last_resid = INFINITY;
@@ -439,6 +439,7 @@ extern "C" int fdlb_init(const fdlb_params *ps, int ncases, void *dev_ws, size_t
     c.prec = c.p.precision;
     c.active = true;
     d.nx = c.nx; d.qh = c.qh; d.qy = c.qy; d.qz = c.qz; d.K = c.K; d.nkx = 2 * c.qh; d.qyz = c.qy * c.qz;
+    d.wide = c.wide ? 1 : 0;
     d.nxp = c.nxp;
     d.ntile_u = (c.nx + UTILE - 1) / UTILE; d.ntile_c = (c.nx + CTILE - 1) / CTILE;
     d.collision = c.p.collision; d.j1_shear = c.p.j1_shear;
@@ -529,7 +530,7 @@ extern "C" int fdlb_moments(fdlb_handle h, int c, double *out) {
   for (int t = 0; t < (ch.nx + CTILE - 1) / CTILE; t++) mt.insert(mt.end(), {c, t, 0, 0});
   int *tmp = h->d_map + 4 * (h->map_cap - mt.size() / 4);
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
-  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, (int)(mt.size() / 4), TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH,
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, (int)(mt.size() / 4), TM_PARTIALS | TM_WRITE_MOM, 0, ch.wide,
                       CTILE, h->stream));
   HIPCHK(hipMemcpyAsync(out, h->hdev[c].mom, sizeof(double) * FDLB_NMOM * ch.nx, hipMemcpyDeviceToHost, h->stream));
   if (!was) { h->hdev[c].active = 0; r = upload_cases(h); if (r) return r; }
@@ -663,7 +664,7 @@ static int refresh_partials(fdlb_ctx *h, int c) {
   HIPCHK(hipMemcpyAsync(tmp, mt.data(), mt.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(hipMemcpyAsync(tmp + mt.size(), mu.data(), mu.size() * 4, hipMemcpyHostToDevice, h->stream));
   HIPCHK(launch_partials(ch.prec, h->d_cases, tmp + mt.size(), (int)(mu.size() / 4), h->waves, h->stream));
-  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, ch.qh > MAXQH, CTILE, h->stream));
+  HIPCHK(launch_table(ch.prec, h->d_cases, tmp, nct, TM_PARTIALS | TM_WRITE_MOM, 0, ch.wide, CTILE, h->stream));
   HIPCHK(hipStreamSynchronize(h->stream));
   return FDLB_OK;
 }

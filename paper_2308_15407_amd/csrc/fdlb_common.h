@@ -52,6 +52,7 @@ struct LatOff {
   int hQ;           // h_Q at the base nodes [nb]
   int ck;           // 1/h_Q'(p_k) [qh]
   int Hy, Hz;       // w_k He_l(p_k)/l!  [qy*qy], [qz*qz]
+  int nb;           // nodes of the base rule (NB or NB_WIDE)
   int fdw;          // one-sided 7-point first-derivative weights, rows for cells 0,1,2 [3*7]
   int xf, xcn;      // cell faces [nx+1] and centres [nx]
   int wlo, whi;     // per cell, the first and last cell its averaging window overlaps [nx] each
@@ -75,6 +76,7 @@ struct CaseDev {
   int collision, j1_shear;
   int active;
   int tlds;             // update blocks stage the projection tables of their tile in LDS
+  int wide;             // the x tables use the NB_WIDE base rule (the wide table pass)
   double eta0, kn, chi0, pr_fixed, ay, dt;
   double tau_pre;       // (5 sqrt(2 pi)/16) Kn chi0 ; 0 when Kn = infinity
   double wallD[2];      // sum over emitted nodes of p_x g^w (left, right)
@@ -130,7 +132,8 @@ struct R1Dev {
 // ---------------------------------------------------------------------------
 
 // Half-range table of g(p) (p-u)^a, a = 0..3, at the positive nodes p_k for the
-// positive half line.  With the base-rule weights G_m = W_m g(P_m)/omega(P_m)
+// positive half line (with a full-range x rule, App. A, the same formulas on
+// the full-range family give the full-range projection at the positive nodes).  With the base-rule weights G_m = W_m g(P_m)/omega(P_m)
 // the Lagrange identity gives X_0[k] = sum_m G_m l_k(P_m); higher powers use
 // (p-u)^a l_k(p) = (p_k-u)^a l_k(p) + h_Q(p)/h_Q'(p_k) sum_{b<a} (p_k-u)^{a-1-b} (p-u)^b.
 // The negative half follows from X^-_a(u) = (-1)^a X^+_a(-u).
@@ -156,7 +159,7 @@ __host__ __device__ inline void hermite_coeffs(double u, double T, int L, double
 inline void host_half_table(const double *lat, const LatOff &lo, int qh, double u, double T, int a,
                             double *X) {
   double rsT = 1.0 / sqrt(T);
-  const int nb = base_nodes(qh);
+  const int nb = lo.nb;
   for (int side = 0; side < 2; side++) {
     double us = side == 0 ? u : -u;
     double G[NB_WIDE], mb[3] = {0, 0, 0};

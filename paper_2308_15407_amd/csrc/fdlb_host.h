@@ -23,6 +23,7 @@ struct CaseHost {
   int kxc, nchunk;                  // kx per velocity chunk, number of chunks
   size_t ws_off[32];                // workspace offsets of this case's arrays
   int prec;                         // active storage precision
+  bool wide;                        // x tables on the NB_WIDE base rule (qx_half > MAXQH or full-range x)
   bool active;
   long steps;
   double last_resid;

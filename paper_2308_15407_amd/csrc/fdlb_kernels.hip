@@ -333,7 +333,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
     if (!WIDE && (mode & TM_WALLS)) wall_block<T>(c, -bm.y - 1, gin);
     return;
   }
-  if ((c.qh > MAXQH) != WIDE) return;
+  if ((c.wide != 0) != WIDE) return;
   constexpr int NBX = WIDE ? NB_WIDE : NB;   // base rule nodes
   constexpr int W = TS + 2 * CHALO;
   __shared__ double s_m[6][W];      // n, ux, uy, T, qx, qy

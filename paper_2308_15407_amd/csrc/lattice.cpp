@@ -169,6 +169,8 @@ int validate(const fdlb_params &p, std::string &why, double *sigma, double *R) {
   if (p.grid != 0 && p.grid != 1) { why = "unknown grid"; return -1; }
   if (p.grid == 1 && !(p.stretch > 0)) { why = "tanh grid needs stretch > 0"; return -1; }
   if (p.precision != 0 && p.precision != 1) { why = "unknown precision"; return -1; }
+  if (p.x_rule != 0 && p.x_rule != 1) { why = "x_rule must be 0 (half-range) or 1 (full-range)"; return -1; }
+  if (p.x_rule == 1 && 2 * p.qx_half > MAXQH_WIDE) { why = "full-range x rule: 2 qx_half must be <= 200"; return -1; }
   if (p.chi_mode != 0 && p.chi_mode != 1) { why = "chi_mode must be 0 (local) or 1 (revised Enskog average)"; return -1; }
   if (p.chi_mode == 1 && p.nx > 4000) { why = "chi_mode 1 supports nx <= 4000 (averaging windows are staged in LDS)"; return -1; }
   if (!(p.t_left > 0 && p.t_right > 0 && p.t_init > 0 && p.n_init > 0)) { why = "temperatures and density must be positive"; return -1; }
@@ -194,7 +196,12 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   c.nxp = fslots(c.nx);
   c.sigma = sigma; c.R = R; c.Lc = 1.0 - sigma;
   c.chi0 = chi_cs(p.eta0);
-  const int Q = c.qh, nb = base_nodes(Q);
+  // x rule: half-range of order Q per half (Sec. III.A.2), or full-range of
+  // order 2Q (App. A; its projections alias through terms of degree >= 2 nb - 2Q,
+  // so it always takes the NB_WIDE base rule)
+  const bool full_x = p.x_rule == 1;
+  const int Q = c.qh, QX = full_x ? 2 * Q : Q, nb = full_x ? NB_WIDE : base_nodes(Q);
+  c.wide = nb == NB_WIDE;
   // lattice offsets
   LatOff &o = c.lo;
   int off = 0;
@@ -208,6 +215,7 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   o.ck = off; off += Q;
   o.Hy = off; off += c.qy * c.qy;
   o.Hz = off; off += c.qz * c.qz;
+  o.nb = nb;
   o.py = off; off += c.qy;
   o.pz = off; off += c.qz;
   o.kmat = off; off += c.qy * c.qy;
@@ -227,35 +235,44 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   c.lat.assign(off, 0.0);
   double *L = c.lat.data();
 
-  // half-range rule of order Q and the base rule of order nb
+  // x rule and the base rule of order nb: the half-range family, or the
+  // full-range one (normal density, alpha_l = sqrt(l), beta = 0, mu0 = 1); the
+  // lattice holds the Q positive nodes p_k (ascending) and their mirror images
   std::vector<ld> a, b, xq, wq, xb, wb;
   ld mu0;
-  int Lmax = std::max(nb, Q) + 2;
-  half_range_recurrence(Lmax, a, b, mu0);
-  gauss_rule(Q, a, b, mu0, xq, wq);
+  int Lmax = std::max(nb, QX) + 2;
+  if (full_x) {
+    a.assign(Lmax + 1, 0); b.assign(Lmax + 1, 0); mu0 = 1;
+    for (int l = 1; l <= Lmax; l++) a[l] = sqrtl((ld)l);
+  } else {
+    half_range_recurrence(Lmax, a, b, mu0);
+  }
+  gauss_rule(QX, a, b, mu0, xq, wq);
   gauss_rule(nb, a, b, mu0, xb, wb);
+  const int k0 = QX - Q;   // first positive node
   c.wx.assign(2 * Q, 0);
   for (int k = 0; k < Q; k++) {
-    L[o.px + k] = (double)xq[k]; L[o.px + Q + k] = -(double)xq[k];
-    c.wx[k] = c.wx[Q + k] = (double)wq[k];
+    L[o.px + k] = (double)xq[k0 + k]; L[o.px + Q + k] = -(double)xq[k0 + k];
+    c.wx[k] = c.wx[Q + k] = (double)wq[k0 + k];
   }
   std::vector<ld> h(Lmax + 2), dh(Lmax + 2), hb(Lmax + 2);
-  // Lagrange basis of the Q lattice nodes at the base nodes (Christoffel-Darboux sum)
-  std::vector<std::vector<ld>> hk(Q, std::vector<ld>(Q + 1));
+  // Lagrange basis of the QX lattice nodes at the base nodes (Christoffel-Darboux
+  // sum), kept for the positive nodes
+  std::vector<std::vector<ld>> hk(Q, std::vector<ld>(QX + 1));
   for (int k = 0; k < Q; k++) {
-    ortho_derivs(xq[k], Q, a, b, mu0, h.data(), dh.data());
-    for (int l = 0; l <= Q; l++) hk[k][l] = h[l];
-    L[o.ck + k] = (double)(1 / dh[Q]);
+    ortho_derivs(xq[k0 + k], QX, a, b, mu0, h.data(), dh.data());
+    for (int l = 0; l <= QX; l++) hk[k][l] = h[l];
+    L[o.ck + k] = (double)(1 / dh[QX]);
   }
   for (int m = 0; m < nb; m++) {
-    ortho_vals(xb[m], Q, a, b, mu0, hb.data());
+    ortho_vals(xb[m], QX, a, b, mu0, hb.data());
     L[o.bP + m] = (double)xb[m];
     L[o.bA + m] = (double)(logl(wb[m]) + xb[m] * xb[m] / 2);
-    L[o.hQ + m] = (double)hb[Q];
+    L[o.hQ + m] = (double)hb[QX];
     for (int k = 0; k < Q; k++) {
       ld s = 0;
-      for (int l = 0; l < Q; l++) s += hk[k][l] * hb[l];
-      L[o.lam + k * nb + m] = (double)(wq[k] * s);
+      for (int l = 0; l < QX; l++) s += hk[k][l] * hb[l];
+      L[o.lam + k * nb + m] = (double)(wq[k0 + k] * s);
     }
   }
   // full-range rules on y and z (normal density, alpha_l = sqrt(l), beta = 0)

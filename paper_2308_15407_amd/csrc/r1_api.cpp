@@ -57,6 +57,7 @@ static int r1_case(const fdlb_params &p, CaseHost &c, std::string &why) {
     return -1;
   }
   if (p.precision != FDLB_F64) { why = "reduced model: FP64 storage only"; return -1; }
+  if (p.x_rule != 0) { why = "reduced model: half-range x rule only"; return -1; }
   fdlb_params q = p;
   if (dim == 1) q.qy = 2;
   q.qz = 2;   // transverse sets of the shared construction that are not used here

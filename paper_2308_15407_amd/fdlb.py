@@ -49,12 +49,13 @@ class fdlb_params(C.Structure):
                 ("qx_half", C.c_int), ("qy", C.c_int), ("qz", C.c_int),
                 ("collision", C.c_int), ("pr_fixed", C.c_double),
                 ("chi_mode", C.c_int), ("j1_shear", C.c_int),
-                ("cfl", C.c_double), ("dt", C.c_double), ("precision", C.c_int)]
+                ("cfl", C.c_double), ("dt", C.c_double), ("precision", C.c_int), ("x_rule", C.c_int)]
 
 
 PARAM_DEFAULTS = dict(flow=0, kn=0.1, eta0=0.05, t_left=1.0, t_right=1.0, uy_left=0.0, uy_right=0.0, ay=0.0,
                       n_init=1.0, t_init=1.0, uy_init=0.0, nx=64, grid=0, stretch=0.0, qx_half=4, qy=3, qz=3,
-                      collision=0, pr_fixed=2.0 / 3.0, chi_mode=0, j1_shear=1, cfl=0.5, dt=0.0, precision=0)
+                      collision=0, pr_fixed=2.0 / 3.0, chi_mode=0, j1_shear=1, cfl=0.5, dt=0.0, precision=0,
+                      x_rule=0)
 
 
 def make_params(d):

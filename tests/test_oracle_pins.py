@@ -110,6 +110,85 @@ def test_full_range_projection_recovers_moments(Q, u, T):
 
 
 # --------------------------------------------------------------------------
+# P1b/P2b  full-range rule on the x axis (App. A; the x_rule = 1 lattice)
+# --------------------------------------------------------------------------
+def _odd_double_factorial(k):
+    return float(np.prod(np.arange(k - 1, 0, -2, dtype=float))) if k > 0 else 1.0
+
+
+@pytest.mark.parametrize("Q", [2, 7, 8, 20, 40, 64, 96])
+def test_full_range_x_rule_vs_numpy_and_gaussian_moments(Q):
+    """The x rule of order Q (roots of He_Q by the scaled recurrence, weights
+    eq:H_wk) is numpy's hermegauss / sqrt(2 pi), and integrates p^s exactly
+    against the normal density for every s < 2Q: (s-1)!! for even s."""
+    p, w = O.gh_rule_n(Q)
+    x, wx = np.polynomial.hermite_e.hermegauss(Q)
+    wx = wx / math.sqrt(2 * math.pi)
+    assert np.max(np.abs(p - x)) < 1e-13 * (1 + np.max(np.abs(x)))
+    assert np.max(np.abs(w - wx) / wx) < 1e-12
+    for s in range(2 * Q):
+        exact = 0.0 if s % 2 else _odd_double_factorial(s)
+        got = np.sum(w * p ** s)
+        scale = max(1.0, float(np.sum(w * np.abs(p) ** s)))
+        assert abs(got - exact) <= 1e-13 * scale * (1 + s), (s, got, exact)
+
+
+@pytest.mark.parametrize("qh", [2, 4, 8, 20, 48])
+@pytest.mark.parametrize("u,T", [(0.0, 1.0), (0.3, 1.2), (-0.4, 0.6), (1.0, 1.5)])
+def test_full_range_x_projection_recovers_gaussian_moments(qh, u, T):
+    """Truncated at N = 2 qh - 1 (eq:H_gk), the projection of g (p-u)^a keeps
+    every moment of order s <= N - a: sum_k X_a[k] p_k^s = E[(p-u)^a p^s]
+    under N(u, T), in closed form through the moments of the standard
+    normal.  Node order: positive roots ascending, then their mirrors."""
+    Q = 2 * qh
+    x, _ = O.gh_rule_n(Q)
+    p = np.concatenate([x[qh:], -x[qh:]])
+    for a in range(4):
+        X = O.project_fullx(qh, u, T, a)
+        for s in range(Q - a):
+            exact = sum(math.comb(s, j) * u ** (s - j) * T ** ((a + j) / 2) *
+                        (0.0 if (a + j) % 2 else _odd_double_factorial(a + j)) for j in range(s + 1))
+            scale = max(1.0, abs(exact), float(np.sum(np.abs(X) * np.abs(p) ** s)))
+            assert abs(np.sum(X * p ** s) - exact) < 1e-13 * scale, (a, s)
+
+
+@pytest.mark.parametrize("u,T", [(0.0, 1.0), (0.3, 1.2), (-0.4, 0.6)])
+def test_full_range_x_projection_converges_to_the_maxwellian(u, T):
+    """For |T - 1| < 1 the full-range Hermite series of the Maxwellian
+    converges: at order 96 the projected populations are w_k g(p_k)/omega(p_k)
+    to rounding, and at order 8 they are not (a truncation is present)."""
+    def gap(qh):
+        x, w = O.gh_rule_n(2 * qh)
+        p = np.concatenate([x[qh:], -x[qh:]])
+        wp = np.concatenate([w[qh:], w[qh:]])
+        g = np.exp(-(p - u) ** 2 / (2 * T)) / math.sqrt(2 * math.pi * T)
+        om = np.exp(-p ** 2 / 2) / math.sqrt(2 * math.pi)
+        return np.max(np.abs(O.project_fullx(qh, u, T, 0) - wp * g / om))
+    assert gap(48) < 1e-15
+    if (u, T) != (0.0, 1.0):
+        assert gap(4) > 1e-6
+
+
+@pytest.mark.parametrize("kw", [dict(t_left=1.0, t_right=1.0, t_init=1.0),
+                                dict(t_left=1.2, t_right=1.2, t_init=1.2, collision=I.SHAKHOV_DENSE)])
+def test_full_range_x_gas_at_rest_is_invariant_and_walls_conserve_mass(kw):
+    """On the x_rule = 1 lattice the walls at the gas temperature keep the
+    gas at rest (J1 = 0, n_w = n), and a perturbed state keeps its mass."""
+    o = O.Oracle(nx=24, qx_half=6, qy=3, qz=3, kn=0.1, eta0=0.2, x_rule=1, **kw)
+    f0 = o.get_f()
+    o.step(150)
+    assert np.max(np.abs(o.get_f() - f0)) < 1e-13
+    cfg = I.config("C1", nx=32, qx_half=6, x_rule=1, collision=I.SHAKHOV_DENSE)
+    o = O.Oracle(**cfg)
+    o.set_state(I.smooth_fields(5, 32, amp=0.05), I.noise(6, o.K, 32, 1e-3))
+    x, J = o.grid()
+    deta = 2.0 / 32
+    m0 = np.sum(o.moments()[0] * J * deta)
+    o.step(100)
+    assert abs(np.sum(o.moments()[0] * J * deta) - m0) < 1e-13 * m0
+
+
+# --------------------------------------------------------------------------
 # P3 / P4  chi, EOS, Pr, tau (Sec. II.A)
 # --------------------------------------------------------------------------
 def test_chi_carnahan_starling():
