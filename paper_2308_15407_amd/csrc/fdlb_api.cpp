@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <string>
@@ -59,6 +60,7 @@ struct fdlb_ctx {
   int kx_user = 0;
   int tileT[4] = {CTILE, CTILE, CTILE, CTILE};   // cells per block of each group's table map
   bool wideT[4] = {false, false, false, false};  // the group holds cases of the wide table pass
+  int qymax[4] = {2, 2, 2, 2};                    // largest Q_y of each group's active cases
   int graph_steps = 0;
   hipGraphExec_t gexec = nullptr;
   hipGraph_t graph = nullptr;
@@ -195,6 +197,10 @@ static std::vector<int> xcd_interleave(const std::vector<int> &logical) {
   return phys;
 }
 
+// update launch form of group G: 0 force-free, else the largest Q_y of its
+// body-force cases (the kernel instance for Q_y <= 4 or <= 8)
+static int force_mode(const fdlb_ctx *h, int G) { return (G & 1) ? h->qymax[G] : 0; }
+
 static int build_maps(fdlb_ctx *h) {
   drop_graph(h);
   std::vector<int> mt[4], mu[4], mn[4];
@@ -209,6 +215,12 @@ static int build_maps(fdlb_ctx *h) {
       blocks[P] += (c.nx + CTILE - 1) / CTILE + 2;
       gwide[P] = gwide[P] || c.wide;
     }
+    for (int G = 0; G < 4; G++) h->qymax[G] = 2;
+    for (const CaseHost &c : h->cases)
+      if (c.active) {
+        const int P = c.prec * 2 + (c.p.ay != 0.0 ? 1 : 0);
+        h->qymax[P] = std::max(h->qymax[P], c.qy);
+      }
     for (int G = 0; G < 4; G++) {
       h->wideT[G] = gwide[G];
       h->tileT[G] = (!gwide[G] && blocks[G] <= SMALL_TABLE_MAP) ? CTILE_SMALL : CTILE;
@@ -303,7 +315,7 @@ static int launch_group_steps(fdlb_ctx *h, int G, long nsteps, hipStream_t s) {
       int mode = TM_PARTIALS | TM_TABLES | TM_WALLS | (stage == 1 ? TM_WRITE_MOM : 0);
       if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], s));
       HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wideT[G], h->tileT[G], s));
-      HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], s));
+      HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, force_mode(h, G), h->lds[G], s));
     }
   return FDLB_OK;
 }
@@ -923,7 +935,7 @@ extern "C" int fdlb_profile(fdlb_handle h, int nrep, double *ms_out) {
         if (h->nN[G] > 0) HIPCHK(launch_nbar(G >> 1, h->d_cases, h->d_mapN[G], h->nN[G], h->lds_n[G], h->stream));
         HIPCHK(launch_table(G >> 1, h->d_cases, h->d_mapT[G], h->nT[G], mode, stage - 1, h->wideT[G], h->tileT[G],
                             h->stream, e[0], e[1]));
-        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, G & 1, h->lds[G], h->stream,
+        HIPCHK(launch_update(G >> 1, stage, h->d_cases, h->d_mapU[G], h->nU[G], h->waves, force_mode(h, G), h->lds[G], h->stream,
                              e[2], e[3]));
       }
     HIPCHK(hipStreamSynchronize(h->stream));

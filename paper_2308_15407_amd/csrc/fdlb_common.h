@@ -25,9 +25,15 @@ constexpr int UTILE = 63;      // cells owned by one update wave (64 faces)
 constexpr int CTILE = FDLB_CTILE;  // cells per table block
 // Table maps that would have at most SMALL_TABLE_MAP blocks of CTILE cells use
 // blocks of CTILE_SMALL cells instead: twice the blocks, each with half the
-// work, for small cases whose table pass is latency-bound.
+// work, for small cases whose table pass is latency-bound (a 512-cell case:
+// 66 blocks of 8 cells instead of 34 of 16).
 constexpr int CTILE_SMALL = 8;
-constexpr int SMALL_TABLE_MAP = 32;
+#ifndef FDLB_SMALL_TABLE_MAP
+#define FDLB_SMALL_TABLE_MAP 64
+#endif
+constexpr int SMALL_TABLE_MAP = FDLB_SMALL_TABLE_MAP;
+// the same rule for the reduced models' stage kernel, with its own threshold
+constexpr int R1_SMALL_MAP = 32;
 constexpr int CHALO = 6;       // moment halo of a table block
 #ifndef FDLB_TABLE_WIDE_MAX
 #define FDLB_TABLE_WIDE_MAX 128

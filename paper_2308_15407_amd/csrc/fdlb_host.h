@@ -79,6 +79,8 @@ constexpr size_t UPDATE_LDS_MAX = 65536;
 #endif
 constexpr int TLDS_MIN_ROWS = FDLB_TLDS_MIN_ROWS;
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds);
+// force: 0 force-free; otherwise the largest Q_y of the launch's (body-force)
+// cases, which selects the kernel instance (Q_y <= 4 or <= 8)
 hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *map, int nblocks, int waves,
                          int force, size_t lds, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 hipError_t launch_fill(int prec, const CaseDev *cases, const int *map, int nblocks, int waves, int use_noise,

@@ -34,6 +34,8 @@ namespace fdlb {
 #define CAS __attribute__((address_space(4)))
 template <bool B>
 struct BoolC { static constexpr bool value = B; };
+template <int N>
+struct IntC { static constexpr int value = N; };
 
 template <typename T>
 __device__ __forceinline__ GAS T *gp(void *p) { return (GAS T *)p; }
@@ -709,8 +711,7 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 #define FDLB_UPDATE_WPE_F64 4
 #endif
 // body-force blocks hold every read of a y-line at once (qy rows of stencil,
-// target and f^n values); their maps are small (one block per tile and chunk
-// of a force-driven case), so they trade occupancy for registers
+// target and f^n values), so they trade occupancy for registers
 #ifndef FDLB_UPDATE_WPE_FORCE
 #define FDLB_UPDATE_WPE_FORCE 2
 #endif
@@ -722,7 +723,7 @@ __device__ __forceinline__ void block_partials(const CaseDev &c, int chunk, int 
 #define FDLB_RING_F32 3
 #endif
 
-template <typename T, int STAGE, bool FORCE>
+template <typename T, int STAGE, bool FORCE, int QYC = MAXQY>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE ? FDLB_UPDATE_WPE_FORCE : (sizeof(T) == 8 ? FDLB_UPDATE_WPE_F64 : FDLB_UPDATE_WPE), 8))) k_update(const CaseDev *__restrict__ cases, const int4 *__restrict__ map) {
   extern __shared__ double lds_dyn[];
   // FP32 storage holds the deviation from the case's background populations
@@ -1043,25 +1044,30 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
     // the LDS of the tables and row buffers is reused by the partial sums
     if (tlds || interior) __syncthreads();
   } else {
-    // body force couples the velocities of one y-line: a wave takes whole lines
+    // body force couples the velocities of one y-line: a wave takes whole
+    // lines.  The line's rows are a compile-time count (one code path per
+    // Q_y), so all its reads (stencils, targets, f^n) form straight-line code
+    // and are in flight together before the first store; a row count known
+    // only at run time would put a branch between the rows and serialise
+    // their reads.  QYC is the largest Q_y of the launch: the instance for
+    // Q_y <= 4 keeps fewer registers live than the one for Q_y <= 8.
     const T ay = (T)c.ay;
     const int nlines = (kx1 - kx0) * qz;
-    for (int line = wv; line < nlines; line += nwv) {
-      const int kx = kx0 + line / qz, kz = line - (line / qz) * qz;
-      const double pxd = lat[lo_px + kx];
-      const bool pos = kx < c_qh;               // positive x nodes come first
-      const Stencil st = stencil(pos);
-      const T4 xv = ldb((const GAS T4 *)(tX + (size_t)kx * tstride * 4), 4 * bc);
-      const T X0 = xv.x, X1 = xv.y, X2 = xv.z, X3 = xv.w;
-      const GAS T *gw = pos ? gwL : gwR;
-      const double nw = pos ? nwl : nwr;
-      // every global read of the line (stencils, targets, f^n) comes before
-      // its first store, so their latencies overlap
-      T cen[MAXQY], adv[MAXQY], tgt[MAXQY], fnv[MAXQY];
+    auto lines = [&](auto qyc) {
+      constexpr int QY = decltype(qyc)::value;
+      for (int line = wv; line < nlines; line += nwv) {
+        const int kx = kx0 + line / qz, kz = line - (line / qz) * qz;
+        const double pxd = lat[lo_px + kx];
+        const bool pos = kx < c_qh;               // positive x nodes come first
+        const Stencil st = stencil(pos);
+        const T4 xv = ldb((const GAS T4 *)(tX + (size_t)kx * tstride * 4), 4 * bc);
+        const T X0 = xv.x, X1 = xv.y, X2 = xv.z, X3 = xv.w;
+        const GAS T *gw = pos ? gwL : gwR;
+        const double nw = pos ? nwl : nwr;
+        T cen[QY], adv[QY], tgt[QY], fnv[QY];
 #pragma unroll
-      for (int ky = 0; ky < MAXQY; ky++) {
-        if (ky < qy) {
-          const int kap = (kx * qy + ky) * qz + kz;
+        for (int ky = 0; ky < QY; ky++) {
+          const int kap = (kx * QY + ky) * qz + kz;
           const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
           const T fh = face(gin + (size_t)kap * fstride, st, pos, fw, cen[ky]);
           const T fr = shift_down1(fh);
@@ -1069,20 +1075,33 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
           tgt[ky] = target(kx, ky * qz + kz, X0, X1, X2, X3);
           fnv[ky] = STAGE == 1 ? (T)0 : ldb(fn + (size_t)kap * fstride, bcf);
         }
-      }
 #pragma unroll
-      for (int ky = 0; ky < MAXQY; ky++) {
-        if (ky < qy) {
-          const int kap = (kx * qy + ky) * qz + kz;
+        for (int ky = 0; ky < QY; ky++) {
+          const int kap = (kx * QY + ky) * qz + kz;
           T sf = 0;
-          const GAS double *km = lat + c.lo.kmat + ky * qy;
+          const GAS double *km = lat + c.lo.kmat + ky * QY;
 #pragma unroll
-          for (int k2 = 0; k2 < MAXQY; k2++)
-            if (k2 < qy) sf += (T)km[k2] * cen[k2];
+          for (int k2 = 0; k2 < QY; k2++) sf += (T)km[k2] * cen[k2];
           if (DF) sf += (T)lat[c.lo.kbg + kap];
           finish(kap, ky, kz, pxd, cen[ky], adv[ky] - ay * sf + (tgt[ky] - cen[ky]) * itau, fnv[ky]);
         }
       }
+    };
+    static_assert(MAXQY == 8, "one code path per full-range order 2..8");
+    switch (qy) {
+      case 2: lines(IntC<2>()); break;
+      case 3: lines(IntC<3>()); break;
+      case 4: lines(IntC<4>()); break;
+      default:
+        if constexpr (QYC > 4) {
+          switch (qy) {
+            case 5: lines(IntC<5>()); break;
+            case 6: lines(IntC<6>()); break;
+            case 7: lines(IntC<7>()); break;
+            default: lines(IntC<8>()); break;
+          }
+        }
+        break;
     }
   }
   block_partials<T>(c, bm.z, c0, acc, is_cell, lds_dyn);
@@ -1258,12 +1277,12 @@ hipError_t launch_table(int prec, const CaseDev *cases, const int *map, int nblo
   return hipGetLastError();
 }
 
-template <typename T, bool FORCE>
+template <typename T, bool FORCE, int QYC = MAXQY>
 static void upd(int stage, dim3 g, dim3 b, size_t lds, hipStream_t s, hipEvent_t e0, hipEvent_t e1,
                 const CaseDev *cases, const int4 *map) {
-  if (stage == 1) launch_k(k_update<T, 1, FORCE>, g, b, lds, s, e0, e1, cases, map);
-  else if (stage == 2) launch_k(k_update<T, 2, FORCE>, g, b, lds, s, e0, e1, cases, map);
-  else launch_k(k_update<T, 3, FORCE>, g, b, lds, s, e0, e1, cases, map);
+  if (stage == 1) launch_k(k_update<T, 1, FORCE, QYC>, g, b, lds, s, e0, e1, cases, map);
+  else if (stage == 2) launch_k(k_update<T, 2, FORCE, QYC>, g, b, lds, s, e0, e1, cases, map);
+  else launch_k(k_update<T, 3, FORCE, QYC>, g, b, lds, s, e0, e1, cases, map);
 }
 
 size_t update_lds_bytes(int prec, int qyz, int kxc, int waves, bool tlds) {
@@ -1278,8 +1297,17 @@ hipError_t launch_update(int prec, int stage, const CaseDev *cases, const int *m
   if (lds > UPDATE_LDS_MAX || lds < (size_t)waves * NRAW * 64 * sizeof(double)) return hipErrorInvalidValue;
   const dim3 g(nblocks), b(64 * waves);
   const int4 *m = (const int4 *)map;
-  if (prec == 0) { if (force) upd<double, true>(stage, g, b, lds, s, e0, e1, cases, m); else upd<double, false>(stage, g, b, lds, s, e0, e1, cases, m); }
-  else { if (force) upd<float, true>(stage, g, b, lds, s, e0, e1, cases, m); else upd<float, false>(stage, g, b, lds, s, e0, e1, cases, m); }
+  // force: 0 none; otherwise the largest Q_y of the launch's cases
+  if (force > MAXQY) return hipErrorInvalidValue;
+  if (prec == 0) {
+    if (force > 4) upd<double, true, 8>(stage, g, b, lds, s, e0, e1, cases, m);
+    else if (force) upd<double, true, 4>(stage, g, b, lds, s, e0, e1, cases, m);
+    else upd<double, false>(stage, g, b, lds, s, e0, e1, cases, m);
+  } else {
+    if (force > 4) upd<float, true, 8>(stage, g, b, lds, s, e0, e1, cases, m);
+    else if (force) upd<float, true, 4>(stage, g, b, lds, s, e0, e1, cases, m);
+    else upd<float, false>(stage, g, b, lds, s, e0, e1, cases, m);
+  }
   return hipGetLastError();
 }
 
@@ -1755,12 +1783,12 @@ static void r1_launch(int stage, const R1Dev *cases, const int2 *m, int nblocks,
 }
 
 // cells per block: 32 up to 128 rows, 16 up to 256, 4 above; maps of at most
-// 256 rows that would have at most SMALL_TABLE_MAP blocks take CTILE_SMALL
+// 256 rows that would have at most R1_SMALL_MAP blocks take CTILE_SMALL
 // cells per block (latency-bound sizes)
 int r1_tile(int rmax, int total_cells) {
   if (rmax > R1_RMAX) return R1_TILE_BIG;
   const int t = rmax <= 128 ? R1_TILE : R1_TILE_2;
-  return (total_cells + t - 1) / t <= SMALL_TABLE_MAP ? CTILE_SMALL : t;
+  return (total_cells + t - 1) / t <= R1_SMALL_MAP ? CTILE_SMALL : t;
 }
 
 template <int RM, int D>
