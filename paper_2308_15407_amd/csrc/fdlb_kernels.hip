@@ -350,6 +350,8 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   __shared__ double s_scr[SCR];
   double (*s_G)[2][NBX + 1] = reinterpret_cast<double (*)[2][NBX + 1]>(s_scr);
   __shared__ double s_red[NT];
+  // full-range z-axis values Z_0, Z_2 per owned cell and node (they depend on T only)
+  __shared__ double s_Z[TS][MAXQY][2];
   // lattice constants, staged by one linear copy of their contiguous block
   // [p_x (2 qh) | P_m | A_m | h_Q(P_m) | lambda (qh rows of NB) | c_k (qh) | H_y | H_z];
   // the lambda rows are padded by one double in LDS (bank spread); the wide
@@ -579,14 +581,24 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
 #pragma unroll
     for (int q = 0; q < 13; q++) s_c[tid][5 + q] = C[q];
   } else if (tid >= 64) {
-    // ---- half-range base weights per owned cell and half (waves 1..3) ----
+    // ---- half-range base weights per owned cell and half, and the z values
+    // per owned cell and node (waves 1..) ----
     static_assert(TS <= 64, "the closure runs on the first wave");
-    for (int it = tid - 64; it < own * 2 * NBX; it += NT - 64) {
-      const int cl = it / (2 * NBX), h = (it / NBX) & 1, m = it % NBX;
-      const double ux = s_m[1][cl + CHALO], T_ = s_m[3][cl + CHALO];
-      const double u = h == 0 ? ux : -ux;
-      const double d = s_P[m] - u;
-      s_G[cl][h][m] = exp(s_A[m] - d * d / (2.0 * T_)) * rsqrt(T_);
+    const int nG = own * 2 * NBX;
+    for (int it = tid - 64; it < nG + own * qz; it += NT - 64) {
+      if (it < nG) {
+        const int cl = it / (2 * NBX), h = (it / NBX) & 1, m = it % NBX;
+        const double ux = s_m[1][cl + CHALO], T_ = s_m[3][cl + CHALO];
+        const double u = h == 0 ? ux : -ux;
+        const double d = s_P[m] - u;
+        s_G[cl][h][m] = exp(s_A[m] - d * d / (2.0 * T_)) * rsqrt(T_);
+      } else {
+        const int cl = (it - nG) % own, kz = (it - nG) / own;
+        double Z[4];
+        full_axis_values(0.0, s_m[3][cl + CHALO], qz, &s_Hz[kz * qz], Z);
+        s_Z[cl][kz][0] = Z[0];
+        s_Z[cl][kz][1] = Z[2];
+      }
     }
   }
   __syncthreads();
@@ -602,7 +614,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
   T *tYZ = (T *)c.tabYZ[P];
   typedef T T4 __attribute__((ext_vector_type(4)));
   const int ngrp = (qh + 1) / 2;
-  const int nXi = own * 2 * ngrp, nYi = own * qyz;
+  const int nXi = own * 2 * ngrp, nYi = own * qy;
   for (int it = tid; it < nXi + nYi; it += blockDim.x) {
     if (it < nXi) {
       const int cl = it % own, rest = it / own, h = rest & 1, k0 = 2 * (rest >> 1);   // cell fastest
@@ -649,26 +661,28 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
         }
       }
     } else {
+      // one item per owned cell and y node: Y_b once, then the qz YZ entries
       const int iy = it - nXi;
-      const int cl = iy % own, yz = iy / own, ky = yz / qz, kz = yz % qz;
-      const double uy = s_c[cl][2], T_ = s_c[cl][3];
-      double Y[4], Z[4];
-      full_axis_values(uy, T_, qy, &s_Hy[ky * qy], Y);
-      full_axis_values(0.0, T_, qz, &s_Hz[kz * qz], Z);
+      const int cl = iy % own, ky = iy / own;
+      double Y[4];
+      full_axis_values(s_c[cl][2], s_c[cl][3], qy, &s_Hy[ky * qy], Y);
       const double *C = &s_c[cl][5];
-      const double Z0 = Z[0], Z2 = Z[2];
-      const double yz0 = C[0] * Y[0] * Z0 + C[2] * Y[1] * Z0 + C[4] * Y[2] * Z0 + C[11] * Y[3] * Z0 +
-                         C[5] * Y[0] * Z2 + C[12] * Y[1] * Z2;
-      const double yz1 = C[1] * Y[0] * Z0 + C[6] * Y[1] * Z0 + C[8] * Y[2] * Z0 + C[9] * Y[0] * Z2;
-      const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
-      const double yz3 = C[7] * Y[0] * Z0;
       const size_t i = (size_t)c0 + cl;
-      T4 yv;
-      yv.x = (T)(yz0 - (sizeof(T) == 4 ? glat[lo.yzbg + yz] : 0.0));
-      yv.y = (T)yz1;
-      yv.z = (T)yz2;
-      yv.w = (T)yz3;
-      *(T4 *)(tYZ + ((size_t)yz * nx + i) * 4) = yv;
+      for (int kz = 0; kz < qz; kz++) {
+        const int yz = ky * qz + kz;
+        const double Z0 = s_Z[cl][kz][0], Z2 = s_Z[cl][kz][1];
+        const double yz0 = C[0] * Y[0] * Z0 + C[2] * Y[1] * Z0 + C[4] * Y[2] * Z0 + C[11] * Y[3] * Z0 +
+                           C[5] * Y[0] * Z2 + C[12] * Y[1] * Z2;
+        const double yz1 = C[1] * Y[0] * Z0 + C[6] * Y[1] * Z0 + C[8] * Y[2] * Z0 + C[9] * Y[0] * Z2;
+        const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
+        const double yz3 = C[7] * Y[0] * Z0;
+        T4 yv;
+        yv.x = (T)(yz0 - (sizeof(T) == 4 ? glat[lo.yzbg + yz] : 0.0));
+        yv.y = (T)yz1;
+        yv.z = (T)yz2;
+        yv.w = (T)yz3;
+        *(T4 *)(tYZ + ((size_t)yz * nx + i) * 4) = yv;
+      }
     }
   }
   if (tid < own) ((T *)c.invtau[P])[c0 + tid] = (T)s_c[tid][4];
