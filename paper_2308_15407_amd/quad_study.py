@@ -24,6 +24,10 @@ and resolves the Knudsen layers of rarefied cases less finely, so that the
 orders found there are lower bounds).
 
     python -m paper_2308_15407_amd.quad_study run [--out PATH] [--cells-per-sigma N]
+    python -m paper_2308_15407_amd.quad_study fine --flows poiseuille --r 4 [--cells-per-sigma 100]
+
+`fine` repeats the rarefied (eta0 = 0.01) cells of one flow on the paper's
+grid (100 cells per sigma) with the revised Enskog contact value.
 
 writes {"flows": {flow: {"R": {R: {eta0: {"q": [...], "eps": [...], "q_min": ...}}}}}}.
 """
@@ -76,9 +80,9 @@ def nx_for(R, cells_per_sigma=CELLS_PER_SIGMA):
     return int(round((R - 1.0) * cells_per_sigma))
 
 
-def case(flow, R, eta0, q, cells_per_sigma=CELLS_PER_SIGMA):
+def case(flow, R, eta0, q, cells_per_sigma=CELLS_PER_SIGMA, chi_mode=0):
     d = dict(I.BASE, kn=kn_for(R, eta0), eta0=eta0, nx=nx_for(R, cells_per_sigma), grid=I.GRID_UNIFORM,
-             qx_half=q, collision=I.SHAKHOV_DENSE, chi_mode=0, precision=0)
+             qx_half=q, collision=I.SHAKHOV_DENSE, chi_mode=chi_mode, precision=0)
     d.update(FLOWS[flow]["case"])
     return d
 
@@ -100,15 +104,16 @@ def q_min(qs, errs, limit=EPS_LIMIT):
     return best
 
 
-def run_flow(flow, cells_per_sigma=CELLS_PER_SIGMA, q_scan=Q_SCAN, max_steps=300000, chunk=50000, log=print):
+def run_flow(flow, cells_per_sigma=CELLS_PER_SIGMA, q_scan=Q_SCAN, max_steps=300000, chunk=50000, log=print,
+             r_values=R_VALUES, eta_values=ETA_VALUES, chi_mode=0):
     from .solver import Solver
     spec = FLOWS[flow]
     keys, cfgs = [], []
-    for R in R_VALUES:
-        for eta0 in ETA_VALUES:
+    for R in r_values:
+        for eta0 in eta_values:
             for q in tuple(q_scan) + (Q_REF,):
                 keys.append((R, eta0, q))
-                cfgs.append(case(flow, R, eta0, q, cells_per_sigma))
+                cfgs.append(case(flow, R, eta0, q, cells_per_sigma, chi_mode))
     log("%s: %d cases" % (flow, len(cfgs)))
     s = Solver(cfgs, graph_steps=100)
     t0 = time.perf_counter()
@@ -145,9 +150,9 @@ def run_flow(flow, cells_per_sigma=CELLS_PER_SIGMA, q_scan=Q_SCAN, max_steps=300
     wall = time.perf_counter() - t0
     log("%s: %.1f s" % (flow, wall))
     prof = {k: prof[i] for i, k in enumerate(keys)}
-    out = {"tol": spec["tol"], "wall_s": round(wall, 2), "R": {}}
-    for R in R_VALUES:
-        for eta0 in ETA_VALUES:
+    out = {"tol": spec["tol"], "wall_s": round(wall, 2), "chi_mode": chi_mode, "R": {}}
+    for R in r_values:
+        for eta0 in eta_values:
             ref = prof[(R, eta0, Q_REF)]
             errs = [eps(prof[(R, eta0, q)], ref) for q in q_scan]
             i_ref = keys.index((R, eta0, Q_REF))
@@ -178,15 +183,34 @@ def run(out=DEFAULT_OUT, cells_per_sigma=CELLS_PER_SIGMA, flows=tuple(FLOWS), ma
     return result
 
 
+def run_fine(out, flow="poiseuille", cells_per_sigma=100, r_values=R_VALUES, eta0=0.01, chi_mode=1,
+             max_steps=1500000, log=print):
+    """The rarefied cells of Table tab:quad on the paper's grid (sigma/100) with
+    the revised Enskog contact value (chi_mode 1), the paper's settings."""
+    result = {"q_ref": Q_REF, "cells_per_sigma": cells_per_sigma, "eps_limit": EPS_LIMIT, "flows": {}}
+    result["flows"][flow] = run_flow(flow, cells_per_sigma, max_steps=max_steps, log=log, r_values=tuple(r_values),
+                                     eta_values=(eta0,), chi_mode=chi_mode)
+    with open(out, "w") as f:
+        json.dump(result, f, indent=1)
+    return result
+
+
 def main():
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["run"])
+    ap.add_argument("cmd", choices=["run", "fine"])
     ap.add_argument("--out", default=DEFAULT_OUT)
-    ap.add_argument("--cells-per-sigma", type=int, default=CELLS_PER_SIGMA)
+    ap.add_argument("--cells-per-sigma", type=int, default=None)
     ap.add_argument("--flows", default=",".join(FLOWS))
-    ap.add_argument("--max-steps", type=int, default=300000)
+    ap.add_argument("--max-steps", type=int, default=None)
+    ap.add_argument("--r", default="4,10", help="fine: confinement ratios")
+    ap.add_argument("--chi-mode", type=int, default=1, help="fine: contact value (1 revised Enskog, 0 local)")
     a = ap.parse_args()
-    run(a.out, a.cells_per_sigma, tuple(a.flows.split(",")), a.max_steps, log=lambda msg: print(msg, flush=True))
+    log = lambda msg: print(msg, flush=True)
+    if a.cmd == "run":
+        run(a.out, a.cells_per_sigma or CELLS_PER_SIGMA, tuple(a.flows.split(",")), a.max_steps or 300000, log=log)
+    else:
+        run_fine(a.out, a.flows.split(",")[0], a.cells_per_sigma or 100, [float(r) for r in a.r.split(",")],
+                 chi_mode=a.chi_mode, max_steps=a.max_steps or 1500000, log=log)
 
 
 if __name__ == "__main__":

@@ -93,3 +93,22 @@ def test_finer_grid_keeps_the_dense_orders_and_raises_the_rarefied_ones():
                 assert e["q_min"] == b["q_min"], (R, eta0)
             else:
                 assert b["q_min"] <= e["q_min"] <= b["q_min"] + 4, (R, eta0, b["q_min"], e["q_min"])
+
+
+def test_paper_grid_reproduces_the_rarefied_poiseuille_order():
+    """The rarefied narrow Poiseuille cell of Table tab:quad (R = 4, eta0 =
+    0.01) on the paper's grid, sigma/100 (Nx = 300): the smallest order with
+    eps below 1 % is 29, the paper's value; the same cell needs 22 at 10 and
+    24 at 20 cells per sigma, so the grid accounts for the difference."""
+    path = os.path.join(Q.HERE, "quad_results_poiseuille_r4_cps100.json")
+    if not os.path.exists(path):
+        pytest.skip("no committed results")
+    res = json.load(open(path))
+    assert res["cells_per_sigma"] == 100
+    e = res["flows"]["poiseuille"]["R"]["4"]["0.01"]
+    assert e["nx"] == Q.nx_for(4.0, 100) == 300
+    assert e["converged_ref"] and all(e["converged"])
+    assert e["q_min"] == Q.q_min(e["q"], e["eps"]) == 29
+    coarse = [json.load(open(p))["flows"]["poiseuille"]["R"]["4"]["0.01"]["q_min"]
+              for p in (Q.DEFAULT_OUT, os.path.join(Q.HERE, "quad_results_poiseuille_cps20.json"))]
+    assert coarse == [22, 24]
