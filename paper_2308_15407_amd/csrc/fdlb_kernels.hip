@@ -158,16 +158,30 @@ __device__ __forceinline__ T weno_face(const T v0, const T v1, const T v2, const
   return (mode == 2) ? F1 : r;
 }
 
-// Face value for interior faces (all three candidates, no ghosts).  In FP64
-// the indicators are scaled into [0, 1] and offset by 1e-30, so the weight
-// products neither vanish nor underflow and no branch is needed: a candidate
-// whose indicator is below 1e-30 of the largest is weighted as if it were
-// 1e-30 of it, which changes the face value by ~1e-15 of the local variation.
-// FP32 keeps the exact zero-set rule of weno_face.
+// Face value for interior faces (all three candidates, no ghosts).  The
+// indicators are scaled into [0, 1] and offset by 1e-30 (FP64) or 1e-9 (FP32),
+// so the weight products neither vanish nor underflow (1e-36 > FLT_MIN) and no
+// branch is needed: a candidate whose indicator is below the offset times the
+// largest is weighted as if it were that fraction of it.  Where indicators
+// vanish, the weights then follow the zero-set rule of weno_face to a relative
+// 1e-60 (FP64) or 1e-18 (FP32) of the surviving ones.
 template <typename T>
 __device__ __forceinline__ T weno_face_interior(const T v0, const T v1, const T v2, const T v3, const T v4) {
   if constexpr (sizeof(T) == 4) {
-    return weno_face<T>(v0, v1, v2, v3, v4, 0);
+    const T F1 = v0 * (T)(1.0 / 3.0) - v1 * (T)(7.0 / 6.0) + v2 * (T)(11.0 / 6.0);
+    const T F2 = -v1 * (T)(1.0 / 6.0) + v2 * (T)(5.0 / 6.0) + v3 * (T)(1.0 / 3.0);
+    const T F3 = v2 * (T)(1.0 / 3.0) + v3 * (T)(5.0 / 6.0) - v4 * (T)(1.0 / 6.0);
+    const T a1 = v0 - (T)2 * v1 + v2, c1 = v0 - (T)4 * v1 + (T)3 * v2;
+    const T a2 = v1 - (T)2 * v2 + v3, c2 = v1 - v3;
+    const T a3 = v2 - (T)2 * v3 + v4, c3 = (T)3 * v2 - (T)4 * v3 + v4;
+    T b1 = (T)(13.0 / 12.0) * a1 * a1 + (T)0.25 * c1 * c1;
+    T b2 = (T)(13.0 / 12.0) * a2 * a2 + (T)0.25 * c2 * c2;
+    T b3 = (T)(13.0 / 12.0) * a3 * a3 + (T)0.25 * c3 * c3;
+    const T r = fast_rcp(fmax(fmax(b1, b2), b3) + (T)1e-30f);
+    b1 = b1 * r + (T)1e-9f; b2 = b2 * r + (T)1e-9f; b3 = b3 * r + (T)1e-9f;
+    const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
+    const T w1 = (T)0.1 * p23 * p23, w2 = (T)0.6 * p13 * p13, w3 = (T)0.3 * p12 * p12;
+    return (w1 * F1 + w2 * F2 + w3 * F3) * fast_rcp(w1 + w2 + w3);
   } else {
     const T F1 = v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0);
     const T F2 = -v1 * (1.0 / 6.0) + v2 * (5.0 / 6.0) + v3 * (1.0 / 3.0);
