@@ -774,6 +774,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
   const GAS T *__restrict__ gwL = gp<T>(c.gw[P][0]);
   const GAS T *__restrict__ gwR = gp<T>(c.gw[P][1]);
   const GAS double *__restrict__ lat = gp<double>(c.lat);
+  // the same constants through the constant address space: read-only for the
+  // kernel, so their (uniform) reads can move ahead of the population stores
+  const CAS double *clat = (const CAS double *)c.lat;
   const int c0 = bm.y * UTILE;
   const int j = c0 + lane;                       // face j (left face of cell j)
   const bool is_cell = lane < UTILE && j < nx;
@@ -833,7 +836,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
     else o = (STAGE == 2) ? (T)0.75 * fnv + (T)0.25 * adv1 : fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
     if (is_cell) stb(out + (size_t)kap * fstride, bw, o);
     {
-      const double pyd = lat[lo_py + ky], pzd = lat[lo_pz + kz];
+      const double pyd = clat[lo_py + ky], pzd = clat[lo_pz + kz];
       const double p2 = pxd * pxd + pyd * pyd + pzd * pzd;
       const double od = is_cell ? (double)o : 0.0;
       acc[0] += od;
@@ -1107,10 +1110,10 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
         for (int ky = 0; ky < QY; ky++) {
           const int kap = (kx * QY + ky) * qz + kz;
           T sf = 0;
-          const GAS double *km = lat + c.lo.kmat + ky * QY;
+          const CAS double *km = clat + c.lo.kmat + ky * QY;
 #pragma unroll
           for (int k2 = 0; k2 < QY; k2++) sf += (T)km[k2] * cen[k2];
-          if (DF) sf += (T)lat[c.lo.kbg + kap];
+          if (DF) sf += (T)clat[c.lo.kbg + kap];
           finish(kap, ky, kz, pxd, cen[ky], adv[ky] - ay * sf + (tgt[ky] - cen[ky]) * itau, fnv[ky]);
         }
       }
