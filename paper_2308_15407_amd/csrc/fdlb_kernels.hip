@@ -47,6 +47,12 @@ template <typename T>
 __device__ __forceinline__ T ldb(const GAS T *row, unsigned bytes) {
   return *(const GAS T *)((const GAS char *)row + bytes);
 }
+// the same through the constant address space, for data the kernel only reads
+// (its reads are free to move ahead of the kernel's global stores)
+template <typename T>
+__device__ __forceinline__ T ldc(const CAS T *row, unsigned bytes) {
+  return *(const CAS T *)((const CAS char *)row + bytes);
+}
 template <typename T>
 __device__ __forceinline__ void stb(GAS T *row, unsigned bytes, T v) {
   *(GAS T *)((GAS char *)row + bytes) = v;
@@ -667,7 +673,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
           const double X3 = dk * dk * dk * x0 + ck * (dk * dk * mb[0] + dk * mb[1] + mb[2]);
           // FP32 storage: the a = 0 table is the deviation from the background factor
           T4 xv;
-          xv.x = (T)(n * x0 - (sizeof(T) == 4 ? glat[lo.xbg + kx] : 0.0));
+          xv.x = (T)(n * x0 - (sizeof(T) == 4 ? ((const CAS double *)lat)[lo.xbg + kx] : 0.0));
           xv.y = (T)(n * sg * X1);
           xv.z = (T)(n * X2);
           xv.w = (T)(n * sg * X3);
@@ -691,7 +697,7 @@ __global__ void __launch_bounds__(NT) k_table(const CaseDev *__restrict__ cases,
         const double yz2 = C[3] * Y[0] * Z0 + C[10] * Y[1] * Z0;
         const double yz3 = C[7] * Y[0] * Z0;
         T4 yv;
-        yv.x = (T)(yz0 - (sizeof(T) == 4 ? glat[lo.yzbg + yz] : 0.0));
+        yv.x = (T)(yz0 - (sizeof(T) == 4 ? ((const CAS double *)lat)[lo.yzbg + yz] : 0.0));
         yv.y = (T)yz1;
         yv.z = (T)yz2;
         yv.w = (T)yz3;
@@ -771,8 +777,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
   GAS T *out = gp<T>(c.f[P][STAGE == 1 ? 1 : (STAGE == 2 ? 2 : 0)]);
   const GAS T *__restrict__ tX = gp<T>(c.tabX[P]);
   const GAS T *__restrict__ tYZ = gp<T>(c.tabYZ[P]);
-  const GAS T *__restrict__ gwL = gp<T>(c.gw[P][0]);
-  const GAS T *__restrict__ gwR = gp<T>(c.gw[P][1]);
+  const CAS T *gwL = (const CAS T *)c.gw[P][0];
+  const CAS T *gwR = (const CAS T *)c.gw[P][1];
+  // the projection tables are written by the table pass and only read here
+  const CAS T *ctX = (const CAS T *)c.tabX[P];
+  const CAS T *ctYZ = (const CAS T *)c.tabYZ[P];
   const GAS double *__restrict__ lat = gp<double>(c.lat);
   // the same constants through the constant address space: read-only for the
   // kernel, so their (uniform) reads can move ahead of the population stores
@@ -863,7 +872,7 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
   // target of one node; FP32: its deviation from the background (see the row loop)
   typedef T T4 __attribute__((ext_vector_type(4)));
   auto target = [&](int kx, int yz, T X0, T X1, T X2, T X3) -> T {
-    const T4 y = ldb((const GAS T4 *)(tYZ + (size_t)yz * tstride * 4), 4 * bc);
+    const T4 y = ldc((const CAS T4 *)(ctYZ + (size_t)yz * tstride * 4), 4 * bc);
     T F = X0 * y.x + X1 * y.y + X2 * y.z + X3 * y.w;
     if (DF) F += X0 * (T)lat[c.lo.yzbg + yz] + (T)lat[c.lo.xbg + kx] * y.x;
     return F;
@@ -974,8 +983,8 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
           y0 = yv.x; y1 = yv.y; y2 = yv.z; y3 = yv.w;
           x0 = xv.x; x1 = xv.y; x2 = xv.z; x3 = xv.w;
         } else {
-          const T4 yv = ldb((const GAS T4 *)(tYZ + (size_t)yz * tstride * 4), 4 * bc);
-          const T4 xv = ldb((const GAS T4 *)(tX + (size_t)kx * tstride * 4), 4 * bc);
+          const T4 yv = ldc((const CAS T4 *)(ctYZ + (size_t)yz * tstride * 4), 4 * bc);
+          const T4 xv = ldc((const CAS T4 *)(ctX + (size_t)kx * tstride * 4), 4 * bc);
           y0 = yv.x; y1 = yv.y; y2 = yv.z; y3 = yv.w;
           x0 = xv.x; x1 = xv.y; x2 = xv.z; x3 = xv.w;
         }
@@ -1091,9 +1100,9 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
         const double pxd = lat[lo_px + kx];
         const bool pos = kx < c_qh;               // positive x nodes come first
         const Stencil st = stencil(pos);
-        const T4 xv = ldb((const GAS T4 *)(tX + (size_t)kx * tstride * 4), 4 * bc);
+        const T4 xv = ldc((const CAS T4 *)(ctX + (size_t)kx * tstride * 4), 4 * bc);
         const T X0 = xv.x, X1 = xv.y, X2 = xv.z, X3 = xv.w;
-        const GAS T *gw = pos ? gwL : gwR;
+        const CAS T *gw = pos ? gwL : gwR;
         const double nw = pos ? nwl : nwr;
         T cen[QY], adv[QY], tgt[QY], fnv[QY];
 #pragma unroll
