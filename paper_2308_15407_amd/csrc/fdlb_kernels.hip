@@ -1093,6 +1093,26 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
     // Q_y <= 4 keeps fewer registers live than the one for Q_y <= 8.
     const T ay = (T)c.ay;
     const int nlines = (kx1 - kx0) * qz;
+    // Q_y <= 4 (many lines per wave): a line's rows pass through LDS row
+    // buffers, one per row, in this wave's slice of the partial-sum area
+    // (NRAW x 64 doubles hold MAXQY buffers).  Buffer index i holds cell
+    // c0-3+i clamped into [0, nx-1], so the five stencil values are shifted
+    // reads of it and equal the clamped loads of face(); ghosts and wall
+    // faces are then substituted per lane.  Per row that is one row load and
+    // a six-lane halo load instead of five stencil loads, which pays where a
+    // wave walks many lines; with one line per wave (Q_y up to 8 on short
+    // grids) the LDS round trip lengthens the line's dependent chain, so that
+    // instance reads the stencils directly.  Both give the same values.
+    constexpr bool LDS_LINES = QYC <= 4;
+    static_assert(MAXQY * ROWBUF <= NRAW * 64, "row buffers of a line fit the wave's partial-sum slice");
+    T *sLine = (T *)(lds_dyn + (size_t)wv * NRAW * 64);
+    const unsigned oa = lane < UTILE ? (unsigned)fslot(min(c0 + lane, nx - 1)) * (unsigned)sizeof(T) : 0x80000000u;
+    const unsigned oh = lane < 3 ? (unsigned)fslot(max(c0 - 3 + lane, 0)) * (unsigned)sizeof(T)
+                                 : (lane < 6 ? (unsigned)fslot(min(c0 + 60 + lane, nx - 1)) * (unsigned)sizeof(T)
+                                             : 0x80000000u);
+    const int kap_base = kx0 * qyz;
+    const unsigned rowbytes = (unsigned)c.nxp * (unsigned)sizeof(T);
+    const auto rs_in = rsrc_of(gin + (size_t)kap_base * fstride, (unsigned)(kx1 - kx0) * (unsigned)qyz * rowbytes);
     auto lines = [&](auto qyc) {
       constexpr int QY = decltype(qyc)::value;
       for (int line = wv; line < nlines; line += nwv) {
@@ -1105,15 +1125,58 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
         const CAS T *gw = pos ? gwL : gwR;
         const double nw = pos ? nwl : nwr;
         T cen[QY], adv[QY], tgt[QY], fnv[QY];
+        if constexpr (!LDS_LINES) {
 #pragma unroll
-        for (int ky = 0; ky < QY; ky++) {
-          const int kap = (kx * QY + ky) * qz + kz;
-          const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
-          const T fh = face(gin + (size_t)kap * fstride, st, pos, fw, cen[ky]);
-          const T fr = shift_down1(fh);
-          adv[ky] = -(T)pxd * dxi * (fr - fh);
-          tgt[ky] = target(kx, ky * qz + kz, X0, X1, X2, X3);
-          fnv[ky] = STAGE == 1 ? (T)0 : ldb(fn + (size_t)kap * fstride, bcf);
+          for (int ky = 0; ky < QY; ky++) {
+            const int kap = (kx * QY + ky) * qz + kz;
+            const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
+            const T fh = face(gin + (size_t)kap * fstride, st, pos, fw, cen[ky]);
+            const T fr = shift_down1(fh);
+            adv[ky] = -(T)pxd * dxi * (fr - fh);
+            tgt[ky] = target(kx, ky * qz + kz, X0, X1, X2, X3);
+            fnv[ky] = STAGE == 1 ? (T)0 : ldb(fn + (size_t)kap * fstride, bcf);
+          }
+        } else {
+          T ra[QY], rh[QY];
+#pragma unroll
+          for (int ky = 0; ky < QY; ky++) {
+            const int kap = (kx * QY + ky) * qz + kz;
+            const int so = (int)((unsigned)(kap - kap_base) * rowbytes);
+            ra[ky] = bld<T>(rs_in, oa, so);
+            rh[ky] = bld<T>(rs_in, oh, so);
+            tgt[ky] = target(kx, ky * qz + kz, X0, X1, X2, X3);
+            fnv[ky] = STAGE == 1 ? (T)0 : ldb(fn + (size_t)kap * fstride, bcf);
+          }
+          // the previous line's reads of the buffers come before these writes
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+          for (int ky = 0; ky < QY; ky++) {
+            T *rb = sLine + ky * ROWBUF;
+            rb[lane < UTILE ? lane + 3 : ROWBUF - 3] = ra[ky];
+            if (lane < 6) rb[lane < 3 ? lane : 63 + lane] = rh[ky];
+          }
+          __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+          __builtin_amdgcn_wave_barrier();
+          __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+#pragma unroll
+          for (int ky = 0; ky < QY; ky++) {
+            const int kap = (kx * QY + ky) * qz + kz;
+            const T fw = (T)(nw * (double)gw[kap] - (DF ? lat[c.lo.bg + kap] : 0.0));
+            const T *rb = sLine + ky * ROWBUF;
+            T v0, v1, v2, v3, v4;
+            if (pos) { v0 = rb[lane]; v1 = rb[lane + 1]; v2 = rb[lane + 2]; v3 = rb[lane + 3]; v4 = rb[lane + 4]; }
+            else { v0 = rb[lane + 5]; v1 = rb[lane + 4]; v2 = rb[lane + 3]; v3 = rb[lane + 2]; v4 = rb[lane + 1]; }
+            if (st.g[0]) v0 = fw;
+            if (st.g[1]) v1 = fw;
+            if (st.g[2]) v2 = fw;
+            cen[ky] = pos ? v3 : v2;
+            const T w = weno_face<T>(v0, v1, v2, v3, v4, st.mode == 3 ? 0 : st.mode);
+            const T fh = (st.mode == 3) ? fw : w;
+            const T fr = shift_down1(fh);
+            adv[ky] = -(T)pxd * dxi * (fr - fh);
+          }
         }
 #pragma unroll
         for (int ky = 0; ky < QY; ky++) {
