@@ -70,6 +70,8 @@ struct LatOff {
   int bgm;          // raw moment sums of the background [NRAW]
   int xbg, yzbg;    // factors of the background, bg[kappa] = xbg[kx] yzbg[ky*qz+kz]: n_init X^0[kx]
                     // [2qh] and Y^0[ky] Z^0[kz] [qyz]; FP32 tables hold n X_0 - xbg and YZ_0 - yzbg
+  int f32;          // FP32 copies of px [2qh], xbg [2qh] and yzbg [qyz], two to a double slot
+                    // (uniform operands of the FP32 update without conversions)
   int total;
 };
 

@@ -164,46 +164,42 @@ __device__ __forceinline__ T weno_face(const T v0, const T v1, const T v2, const
   return (mode == 2) ? F1 : r;
 }
 
-// Face value for interior faces (all three candidates, no ghosts).  The
-// indicators are scaled into [0, 1] and offset by 1e-30 (FP64) or 1e-9 (FP32),
-// so the weight products neither vanish nor underflow (1e-36 > FLT_MIN) and no
+// Face value for interior faces (all three candidates, no ghosts), written
+// in the first differences e_k = v_{k+1} - v_k of the stencil: every
+// candidate is v2 plus a combination of them, and so is every second
+// difference in the indicators, so the face is v2 plus the weighted mean of
+// the candidates' increments.  The indicators are taken as (12/13) beta_q =
+// a_q^2 + (3/13) c_q^2 (a common factor, which the normalisation removes),
+// scaled into [0, 1] and offset by 1e-30 (FP64) or 1e-9 (FP32), so the
+// weight products neither vanish nor underflow (1e-36 > FLT_MIN) and no
 // branch is needed: a candidate whose indicator is below the offset times the
 // largest is weighted as if it were that fraction of it.  Where indicators
 // vanish, the weights then follow the zero-set rule of weno_face to a relative
-// 1e-60 (FP64) or 1e-18 (FP32) of the surviving ones.
+// 1e-60 (FP64) or 1e-18 (FP32) of the surviving ones.  The ideal weights d_q
+// are folded into the increments (G_q = d_q (F_q - v2)) and into the
+// normalising sum.
 template <typename T>
 __device__ __forceinline__ T weno_face_interior(const T v0, const T v1, const T v2, const T v3, const T v4) {
-  if constexpr (sizeof(T) == 4) {
-    const T F1 = v0 * (T)(1.0 / 3.0) - v1 * (T)(7.0 / 6.0) + v2 * (T)(11.0 / 6.0);
-    const T F2 = -v1 * (T)(1.0 / 6.0) + v2 * (T)(5.0 / 6.0) + v3 * (T)(1.0 / 3.0);
-    const T F3 = v2 * (T)(1.0 / 3.0) + v3 * (T)(5.0 / 6.0) - v4 * (T)(1.0 / 6.0);
-    const T a1 = v0 - (T)2 * v1 + v2, c1 = v0 - (T)4 * v1 + (T)3 * v2;
-    const T a2 = v1 - (T)2 * v2 + v3, c2 = v1 - v3;
-    const T a3 = v2 - (T)2 * v3 + v4, c3 = (T)3 * v2 - (T)4 * v3 + v4;
-    T b1 = (T)(13.0 / 12.0) * a1 * a1 + (T)0.25 * c1 * c1;
-    T b2 = (T)(13.0 / 12.0) * a2 * a2 + (T)0.25 * c2 * c2;
-    T b3 = (T)(13.0 / 12.0) * a3 * a3 + (T)0.25 * c3 * c3;
-    const T r = fast_rcp(fmax(fmax(b1, b2), b3) + (T)1e-30f);
-    b1 = b1 * r + (T)1e-9f; b2 = b2 * r + (T)1e-9f; b3 = b3 * r + (T)1e-9f;
-    const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
-    const T w1 = (T)0.1 * p23 * p23, w2 = (T)0.6 * p13 * p13, w3 = (T)0.3 * p12 * p12;
-    return (w1 * F1 + w2 * F2 + w3 * F3) * fast_rcp(w1 + w2 + w3);
-  } else {
-    const T F1 = v0 * (1.0 / 3.0) - v1 * (7.0 / 6.0) + v2 * (11.0 / 6.0);
-    const T F2 = -v1 * (1.0 / 6.0) + v2 * (5.0 / 6.0) + v3 * (1.0 / 3.0);
-    const T F3 = v2 * (1.0 / 3.0) + v3 * (5.0 / 6.0) - v4 * (1.0 / 6.0);
-    const T a1 = v0 - 2.0 * v1 + v2, c1 = v0 - 4.0 * v1 + 3.0 * v2;
-    const T a2 = v1 - 2.0 * v2 + v3, c2 = v1 - v3;
-    const T a3 = v2 - 2.0 * v3 + v4, c3 = 3.0 * v2 - 4.0 * v3 + v4;
-    T b1 = (13.0 / 12.0) * a1 * a1 + 0.25 * c1 * c1;
-    T b2 = (13.0 / 12.0) * a2 * a2 + 0.25 * c2 * c2;
-    T b3 = (13.0 / 12.0) * a3 * a3 + 0.25 * c3 * c3;
-    const T r = fast_rcp(fmax(fmax(b1, b2), b3) + 1e-300);
-    b1 = b1 * r + 1e-30; b2 = b2 * r + 1e-30; b3 = b3 * r + 1e-30;
-    const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
-    const T w1 = 0.1 * p23 * p23, w2 = 0.6 * p13 * p13, w3 = 0.3 * p12 * p12;
-    return (w1 * F1 + w2 * F2 + w3 * F3) * fast_rcp(w1 + w2 + w3);
-  }
+  constexpr T off = sizeof(T) == 4 ? (T)1e-9f : (T)1e-30;
+  constexpr T tiny = sizeof(T) == 4 ? (T)1e-30f : (T)1e-300;
+  const T e0 = v1 - v0, e1 = v2 - v1, e2 = v3 - v2, e3 = v4 - v3;
+  const T a1 = e1 - e0, a2 = e2 - e1, a3 = e3 - e2;
+  // c_q up to sign: v0 - 4 v1 + 3 v2, v1 - v3, 3 v2 - 4 v3 + v4
+  const T c1 = e0 - (T)3 * e1, c2 = e1 + e2, c3 = e3 - (T)3 * e2;
+  T b1 = a1 * a1 + (T)(3.0 / 13.0) * (c1 * c1);
+  T b2 = a2 * a2 + (T)(3.0 / 13.0) * (c2 * c2);
+  T b3 = a3 * a3 + (T)(3.0 / 13.0) * (c3 * c3);
+  const T r = fast_rcp(fmax(fmax(b1, b2), b3) + tiny);
+  b1 = b1 * r + off; b2 = b2 * r + off; b3 = b3 * r + off;
+  const T p12 = b1 * b2, p13 = b1 * b3, p23 = b2 * b3;
+  const T w1 = p23 * p23, w2 = p13 * p13, w3 = p12 * p12;
+  // d_q (F_q - v2): F1 - v2 = (5 e1 - 2 e0)/6, F2 - v2 = (e1 + 2 e2)/6, F3 - v2 = (4 e2 - e3)/6
+  const T G1 = e1 * (T)(0.5 / 6.0) - e0 * (T)(0.2 / 6.0);
+  const T G2 = e1 * (T)(0.6 / 6.0) + e2 * (T)(1.2 / 6.0);
+  const T G3 = e2 * (T)(1.2 / 6.0) - e3 * (T)(0.3 / 6.0);
+  const T num = w1 * G1 + w2 * G2 + w3 * G3;
+  const T den = (T)0.1 * w1 + (T)0.6 * w2 + (T)0.3 * w3;
+  return v2 + num * fast_rcp(den);
 }
 
 __device__ __forceinline__ double chi_cs(double eta) {
@@ -922,6 +918,14 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
     }
     dxi = (T)invdx[jc];
     itau = invtau[jc];
+    // the RK3 weight of the advanced value (eq:rk3) folded into the lane's
+    // factors: o = (1 - ws) f^n + ws cen - (p_x ws dt/dx)(fr - fh) + (ws dt/tau)(F - cen)
+    constexpr double WS = STAGE == 1 ? 1.0 : (STAGE == 2 ? 0.25 : 2.0 / 3.0);
+    const T adx = (T)WS * dt * dxi, ait = (T)WS * dt * itau;
+    // FP32: p_x and the background factors as floats (uniform operands
+    // without conversions): fpx[kx], fxb[kx], fyzb[yz]
+    const CAS float *fpx = (const CAS float *)(c.lat + c.lo.f32);
+    const CAS float *fxb = fpx + 2 * c_qh, *fyzb = fpx + 4 * c_qh;
     const bool interior = c0 >= 3 && c0 + 66 <= nx;
     // interior tiles: per-wave LDS row buffers after the tables.  The row load
     // takes the tile's 64 aligned slots (cells c0 .. c0+62 and the padding
@@ -934,8 +938,6 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
                                              : 0x80000000u);
     const CAS double *__restrict__ phi = (const CAS double *)(c.lat + lo_phi);
     const CAS double *__restrict__ bgc = (const CAS double *)(c.lat + lo_bg);
-    const CAS double *__restrict__ xb = (const CAS double *)(c.lat + c.lo.xbg);
-    const CAS double *__restrict__ yzb = (const CAS double *)(c.lat + c.lo.yzbg);
     const unsigned rowbytes = (unsigned)c.nxp * (unsigned)sizeof(T);
     // one buffer resource per population array over the chunk's rows: a row
     // is a scalar byte offset, a cell the lane's offset (lanes past the
@@ -1023,12 +1025,11 @@ __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(FORCE 
         T F = x0 * y0 + x1 * y1 + x2 * y2 + x3 * y3;
         // FP32: F - bg = dX0 dYZ0 + dX0 yzbg + xbg dYZ0 + sum_{a>0} X_a YZ_a, every
         // term of the size of the deviation
-        if (DF) F += x0 * (T)yzb[yz] + (T)xb[kx] * y0;
-        const T L = (-(T)pxd * dxi) * (fr - fh) + (F - cen) * itau;
-        const T adv1 = cen + dt * L;
-        T o;
-        if (STAGE == 1) o = adv1;
-        else o = (STAGE == 2) ? (T)0.75 * d.fnv + (T)0.25 * adv1 : d.fnv * (T)(1.0 / 3.0) + (T)(2.0 / 3.0) * adv1;
+        if (DF) F += x0 * (T)fyzb[yz] + (T)fxb[kx] * y0;
+        const T pxT = DF ? (T)fpx[kx] : (T)pxd;
+        T o = STAGE == 1 ? cen : (T)(1.0 - WS) * d.fnv + (T)WS * cen;
+        o -= (pxT * adx) * (fr - fh);
+        o += ait * (F - cen);
         // lanes without a cell store past the row range (dropped), so the
         // store needs no branch
         bst<T>(rs_out, is_cell ? bw : 0x80000000u, (int)((unsigned)r * rowbytes), o);

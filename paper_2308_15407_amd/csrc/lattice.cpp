@@ -231,6 +231,7 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
   o.bgm = off; off += NRAW;
   o.xbg = off; off += 2 * Q;
   o.yzbg = off; off += c.qy * c.qz;
+  o.f32 = off; off += (4 * Q + c.qy * c.qz + 1) / 2;
   o.total = off;
   c.lat.assign(off, 0.0);
   double *L = c.lat.data();
@@ -407,6 +408,15 @@ int build_case(const fdlb_params &p, CaseHost &c, std::string &why) {
           for (int k2 = 0; k2 < c.qy; k2++) sf += L[o.kmat + ky * c.qy + k2] * L[o.bg + (kx * c.qy + k2) * c.qz + kz];
           L[o.kbg + (kx * c.qy + ky) * c.qz + kz] = sf;
         }
+  }
+  {
+    std::vector<float> f(4 * Q + c.qy * c.qz);
+    for (int kx = 0; kx < 2 * Q; kx++) {
+      f[kx] = (float)L[o.px + kx];
+      f[2 * Q + kx] = (float)L[o.xbg + kx];
+    }
+    for (int yz = 0; yz < c.qy * c.qz; yz++) f[4 * Q + yz] = (float)L[o.yzbg + yz];
+    std::memcpy(&L[o.f32], f.data(), f.size() * sizeof(float));
   }
   return 0;
 }
