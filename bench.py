@@ -57,7 +57,7 @@ def parse():
                     help="held-out cases of the time-to-steady leg (every arm solves the same cases)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the all-cores oracle sample")
     # profiler mode
-    ap.add_argument("--profile-case", default=None, help="short fixed run of a workload (R2, C2, C3, sweep)")
+    ap.add_argument("--profile-case", default=None, help="short fixed run of a workload (R2, C2, C3, sweep, sweep1024)")
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("KX_PER_CHUNK", "WAVES"))
     ap.add_argument("--copy-mib", type=int, default=256)
@@ -298,9 +298,9 @@ def profile_case(a):
     if a.reduced:
         s = ReducedSolver(I.config(a.profile_case, precision=0))
     else:
-        if a.profile_case == "sweep":
+        if a.profile_case in ("sweep", "sweep1024"):
             from paper_2308_15407_amd import sweep
-            cfg = sweep.sweep_cases(256, precision=a.precision)
+            cfg = sweep.sweep_cases(1024 if a.profile_case == "sweep1024" else 256, precision=a.precision)
         else:
             cfg = I.config(a.profile_case, precision=a.precision)
         s = Solver(cfg)
