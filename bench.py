@@ -151,9 +151,10 @@ def dominant_roofline(tile, prof, cfg, nodes, prec, workload):
     chunks = [-(-2 * c["qx_half"] // min(kxc, 2 * c["qx_half"])) for c in cases]
     tab = table_roofline(prof, cases, prec, workload, chunks)
     up_ms = sum(prof[1 + 3 * prec:4 + 3 * prec])
-    dom, other = (tab, upd) if 3 * prof[0] > up_ms else (upd, tab)
+    table_dominant = 3 * prof[0] > up_ms
+    dom, other = (tab, upd) if table_dominant else (upd, tab)
     dom = dict(dom)
-    dom["share_of_kernel_time"] = round((3 * prof[0] if dom is tab else up_ms) / (3 * prof[0] + up_ms), 3)
+    dom["share_of_kernel_time"] = round((3 * prof[0] if table_dominant else up_ms) / (3 * prof[0] + up_ms), 3)
     dom["other_kernel"] = other
     return dom
 

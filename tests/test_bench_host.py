@@ -1,0 +1,33 @@
+"""Host arithmetic of bench.py's roofline objects (no GPU): which kernel is
+priced as dominant, its share of the step's kernel time, and the algorithmic
+bytes per launch."""
+import pytest
+
+import bench
+import fdlb_inputs as I
+
+
+def _prof(table, upd, prec):
+    # [table, update 1..3 FP64, update 1..3 FP32] in ms, as fdlb_profile returns them
+    p = [table, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0]
+    p[1 + 3 * prec:4 + 3 * prec] = upd
+    return p
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_dominant_kernel_and_its_share(prec):
+    cfg = I.config("C2", precision=prec)
+    nodes = cfg["nx"] * 2 * cfg["qx_half"] * cfg["qy"] * cfg["qz"]
+    # table pass larger: 3 x 0.008 against 3 x 0.005
+    r = bench.dominant_roofline((1, 8), _prof(0.008, [0.005] * 3, prec), cfg, nodes, prec, "C2")
+    assert r["kernel"].startswith("k_table")
+    assert r["share_of_kernel_time"] == pytest.approx(0.024 / 0.039, abs=1e-3)
+    assert r["other_kernel"]["kernel"].startswith("k_update")
+    # update larger
+    r = bench.dominant_roofline((1, 8), _prof(0.004, [0.005, 0.006, 0.007], prec), cfg, nodes, prec, "C2")
+    assert r["kernel"].startswith("k_update")
+    assert r["share_of_kernel_time"] == pytest.approx(0.018 / 0.030, abs=1e-3)
+    # stage 2 is priced: three passes of the population element size over every node
+    s = 8 if prec == 0 else 4
+    assert r["algorithmic_bytes_per_launch"] == 3 * s * nodes
+    assert r["achieved"] == pytest.approx(3 * s * nodes / 0.006e-3 / 1e9, rel=1e-3)
