@@ -28,6 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+BF16_MFMA_PEAK_TFLOPS = 2500.0   # MI355X dense BF16 matrix peak
 
 
 WORKLOADS = {
@@ -57,7 +58,7 @@ def parse():
                     help="held-out cases of the time-to-steady leg (every arm solves the same cases)")
     ap.add_argument("--cpu-seconds", type=float, default=12.0, help="budget of the all-cores oracle sample")
     # profiler mode
-    ap.add_argument("--profile-case", default=None, help="short fixed run of a workload (R2, C2, C3, sweep, sweep1024)")
+    ap.add_argument("--profile-case", default=None, help="short fixed run of a workload (R2, C2, C3, sweep, sweep1024, mlp)")
     ap.add_argument("--precision", type=int, default=0)
     ap.add_argument("--tiling", type=int, nargs=2, default=None, metavar=("KX_PER_CHUNK", "WAVES"))
     ap.add_argument("--copy-mib", type=int, default=256)
@@ -248,6 +249,67 @@ def reduced_leg(steps, workload="R2", warmup=5):
             "values": vals, "effective_GBps_whole_step": round(eff, 1), "frac_of_hbm_peak": round(eff / HBM_PEAK_GBS, 4)}
 
 
+def mlp_flops_per_step(batch, n_in=10, width=256, depth=4, n_out=640):
+    """GEMM flops of one training step of the warm-start network: per layer the
+    forward product and the weight gradient, and the input gradient of every
+    layer but the first (2 flops per multiply-add)."""
+    dims = [n_in] + [width] * depth + [n_out]
+    f = 0
+    for l in range(len(dims) - 1):
+        mac = batch * dims[l] * dims[l + 1]
+        f += 2 * mac * (3 if l > 0 else 2)
+    return f
+
+
+def mlp_leg(steps=50, batch=4096, gemm_n=4096, gemm_reps=5):
+    """The warm-start network's training step at its full shape (10 -> 4 x 256
+    GELU -> 640, BF16 on MFMA with FP32 accumulation, AdamW), batch 4096: its
+    GEMM flops over the step time against the dense BF16 MFMA peak; and the
+    library's BF16 GEMM kernel alone on a square product of edge gemm_n."""
+    import time
+    import torch
+    from paper_2308_15407_amd import fdlb as F
+    from paper_2308_15407_amd.mlp import WarmStartNet
+    net = WarmStartNet(n_in=10, width=256, depth=4, n_out=640, max_batch=batch)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(20230829)
+    x = torch.randn(batch, 10, device="cuda", generator=g)
+    t = torch.randn(batch, 640, device="cuda", generator=g)
+    for _ in range(5):
+        net.train_step(x, t, 1e-4)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(net.stream)
+    for _ in range(steps):
+        net.train_step(x, t, 1e-4)
+    b.record(net.stream)
+    b.synchronize()
+    ms = a.elapsed_time(b) / steps
+    flops = mlp_flops_per_step(batch)
+    net.close()
+    # the GEMM kernel alone (each call synchronises; wall clock over gemm_reps calls)
+    n = gemm_n
+    A = torch.randn(n, n, device="cuda", generator=g).to(torch.bfloat16)
+    B = torch.randn(n, n, device="cuda", generator=g).to(torch.bfloat16)
+    Cm = torch.empty(n, n, device="cuda", dtype=torch.float32)
+    st = torch.cuda.current_stream().cuda_stream
+    F.fdlb_mlp_gemm_bf16(A.data_ptr(), B.data_ptr(), Cm.data_ptr(), n, n, n, n, 1, n, 1, n, st)
+    t0 = time.perf_counter()
+    for _ in range(gemm_reps):
+        F.fdlb_mlp_gemm_bf16(A.data_ptr(), B.data_ptr(), Cm.data_ptr(), n, n, n, n, 1, n, 1, n, st)
+    gms = (time.perf_counter() - t0) / gemm_reps * 1e3
+    step_tf = flops / (ms * 1e-3) / 1e12
+    gemm_tf = 2.0 * n ** 3 / (gms * 1e-3) / 1e12
+    return {"workload": "warm-start MLP 10 -> 4 x 256 GELU -> 640, BF16 MFMA, batch %d, one AdamW training step"
+                        % batch,
+            "ms_per_step": round(ms, 5), "gemm_flops_per_step": flops,
+            "roofline": {"bound": "mfma", "achieved": round(step_tf, 2), "peak": BF16_MFMA_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": round(step_tf / BF16_MFMA_PEAK_TFLOPS, 5)},
+            "gemm_kernel": {"shape": "%d^3" % n, "ms": round(gms, 4), "achieved": round(gemm_tf, 1),
+                            "peak": BF16_MFMA_PEAK_TFLOPS, "unit": "TFLOP/s",
+                            "frac": round(gemm_tf / BF16_MFMA_PEAK_TFLOPS, 4)}}
+
+
 def time_to_steady_leg(n_cases, tol=1e-8, max_steps=400000):
     """Wall-clock time to r < tol per case on one sample of held-out cases:
     plain FP64 cold start (one case at a time) against the batched arms (all
@@ -296,6 +358,9 @@ def profile_case(a):
     import fdlb_inputs as I
     from paper_2308_15407_amd import fdlb as F
     from paper_2308_15407_amd.solver import ReducedSolver, Solver
+    if a.profile_case == "mlp":
+        print(json.dumps(mlp_leg(steps=a.steps, gemm_reps=3)), flush=True)
+        return
     if a.reduced:
         s = ReducedSolver(I.config(a.profile_case, precision=0))
     else:
@@ -387,6 +452,7 @@ def main():
         out["sweep"] = sweep_leg(args.sweep_steps, args.retune)
         out["sweep_r1"] = sweep_r1_leg(args.r1_steps, args.retune)
         out["time_to_steady"] = time_to_steady_leg(args.tts_cases)
+        out["mlp"] = mlp_leg()
     out["cpu_baseline"] = None if args.no_cpu else cpu_baseline(cfg, budget_s=args.cpu_seconds)
     print(json.dumps(out))
 

@@ -1,6 +1,7 @@
 // mlp_api.cpp -- C ABI of the warm-start network (declared in include/fdlb.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <string>
@@ -39,6 +40,7 @@ struct fdlb_mlp_ctx {
   float *dZf, *dH;
   double *part;
   float *loss;
+  float *ksp;                           // split-K partial products of the weight gradients
   long t;
 };
 
@@ -72,6 +74,9 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
   for (int l = 0; l < L; l++) pz[l] = take(4 * (size_t)maxb * dout[l]);
   char *pdzb = take(2 * (size_t)maxb * maxw), *pdzf = take(4 * (size_t)maxb * maxw), *pdh = take(4 * (size_t)maxb * maxw);
   char *ppart = take(8 * 256), *ploss = take(8);
+  long maxio = 0;
+  for (int l = 0; l < L; l++) maxio = std::max(maxio, (long)din[l] * dout[l]);
+  char *pksp = take(4 * (size_t)MLP_SPLITK_MAX * maxio);
   if (c) {
     c->nin = nin; c->width = w; c->depth = depth; c->nout = nout; c->maxb = maxb; c->L = L;
     c->din = din; c->dout = dout; c->woff = woff; c->boff = boff; c->wboff = wboff; c->P = P; c->PW = PW;
@@ -80,7 +85,7 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
     c->H.resize(L); c->Z.resize(L);
     for (int l = 0; l < L; l++) { c->H[l] = (uint16_t *)ph[l]; c->Z[l] = (float *)pz[l]; }
     c->dZb = (uint16_t *)pdzb; c->dZf = (float *)pdzf; c->dH = (float *)pdh;
-    c->part = (double *)ppart; c->loss = (float *)ploss;
+    c->part = (double *)ppart; c->loss = (float *)ploss; c->ksp = (float *)pksp;
   }
   return off;
 }
@@ -173,7 +178,7 @@ static int backward(fdlb_mlp h, const float *t_dev, int M) {
   for (int l = h->L - 1; l >= 0; l--) {
     const int in = h->din[l], out = h->dout[l];
     // dW = dZ^T H_l : A(o, m) = dZ[m][o], B(m, i) = H_l[m][i]
-    MCHK(mlp_gemm(h->dZb, h->H[l], h->g + h->woff[l], out, in, M, 1, out, in, 1, in, 0, h->s));
+    MCHK(mlp_gemm_splitk(h->dZb, h->H[l], h->g + h->woff[l], out, in, M, 1, out, in, 1, in, 0, h->ksp, h->s));
     MCHK(mlp_colsum(h->dZf, h->g + h->boff[l], M, out, h->s));
     if (l > 0) {
       // dH = dZ W_l : A = dZ [M x out], B(o, i) = W_l[o][i]

@@ -6,6 +6,14 @@
 namespace fdlb {
 hipError_t mlp_gemm(const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K, long sam, long sak,
                     long sbk, long sbn, int ldc, int accumulate, hipStream_t s);
+// split-K GEMM for products with few output tiles and a long depth (the weight
+// gradients, whose depth is the batch): up to MLP_SPLITK_MAX slices of the
+// depth write partial products into `partial` (slices x M x N floats), which a
+// second kernel adds in slice order into C
+constexpr int MLP_SPLITK_MAX = 16;
+int mlp_splitk_slices(int M, int N, int K);
+hipError_t mlp_gemm_splitk(const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K, long sam, long sak,
+                           long sbk, long sbn, int ldc, int accumulate, float *partial, hipStream_t s);
 hipError_t mlp_bias_act(float *Z, const float *b, uint16_t *H, int M, int N, int act, hipStream_t s);
 hipError_t mlp_gelu_bwd(const float *dH, const float *Z, uint16_t *dZb, float *dZf, long n, hipStream_t s);
 hipError_t mlp_mse(const float *Y, const float *T, uint16_t *dYb, float *dYf, double *part, long n, float *loss,

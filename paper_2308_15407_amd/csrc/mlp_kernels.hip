@@ -29,22 +29,26 @@ constexpr int GK = 16;   // depth per MFMA step
 
 __global__ void __launch_bounds__(256) k_gemm_bf16(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                    float *__restrict__ C, int M, int N, int K, long sam, long sak,
-                                                   long sbk, long sbn, int ldc, int accumulate) {
+                                                   long sbk, long sbn, int ldc, int accumulate, int kchunk,
+                                                   long cslice) {
   __shared__ uint16_t sA[GT][GK + 4];   // [m][k]
   __shared__ uint16_t sB[GT][GK + 4];   // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
+  // split K: block z takes depths [kb, ke) and writes its own slice of C
+  const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
+  C += blockIdx.z * cslice;
   const int wr = wv >> 1, wc = wv & 1;
   v4f acc[2][2];
   for (int i = 0; i < 2; i++)
     for (int j = 0; j < 2; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < K; k0 += GK) {
+  for (int k0 = kb; k0 < ke; k0 += GK) {
     // stage: 64x16 elements of A and of B, 4 per thread each
     for (int e = tid; e < GT * GK; e += 256) {
       const int r = e / GK, kk = e % GK;
       const int gm = m0 + r, gn = n0 + r, gk = k0 + kk;
-      sA[r][kk] = (gm < M && gk < K) ? A[(long)gm * sam + (long)gk * sak] : (uint16_t)0;
-      sB[r][kk] = (gn < N && gk < K) ? B[(long)gk * sbk + (long)gn * sbn] : (uint16_t)0;
+      sA[r][kk] = (gm < M && gk < ke) ? A[(long)gm * sam + (long)gk * sak] : (uint16_t)0;
+      sB[r][kk] = (gn < N && gk < ke) ? B[(long)gk * sbk + (long)gn * sbn] : (uint16_t)0;
     }
     __syncthreads();
     const int row = lane & 15, kq = (lane >> 4) * 4;
@@ -128,13 +132,44 @@ __global__ void k_sum_parts(const double *__restrict__ part, int nparts, long n,
   }
 }
 
-// db[n] = sum_m dZ[m][n]   (fixed order per column)
-__global__ void k_colsum(const float *__restrict__ dZ, float *__restrict__ db, int M, int N) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  float s = 0;
-  for (int m = 0; m < M; m++) s += dZ[(long)m * N + n];
-  db[n] = s;
+// db[n] = sum_m dZ[m][n]: a 1024-thread block per 64 columns; wave w sums rows
+// w, w + 16, ... of its lane's column in four interleaved partial sums (loads
+// coalesced along the row), then the 16 wave sums are added in wave order
+// (a fixed order: the result does not depend on timing)
+__global__ void __launch_bounds__(1024) k_colsum(const float *__restrict__ dZ, float *__restrict__ db, int M, int N) {
+  __shared__ float red[16][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  if (n < N) {
+    int m = wv;
+    for (; m + 48 < M; m += 64) {
+      s0 += dZ[(long)m * N + n];
+      s1 += dZ[(long)(m + 16) * N + n];
+      s2 += dZ[(long)(m + 32) * N + n];
+      s3 += dZ[(long)(m + 48) * N + n];
+    }
+    for (; m < M; m += 16) s0 += dZ[(long)m * N + n];
+  }
+  red[wv][lane] = (s0 + s1) + (s2 + s3);
+  __syncthreads();
+  if (wv == 0 && n < N) {
+    float s = 0.f;
+    for (int w = 0; w < 16; w++) s += red[w][lane];
+    db[n] = s;
+  }
+}
+
+// C[m][n] (ldc) (+)= sum over z of P[z][m][n] (slices of M x N), in z order
+__global__ void k_splitk_sum(const float *__restrict__ P, float *__restrict__ C, int M, int N, int S, int ldc,
+                             int accumulate) {
+  const long mn = (long)M * N;
+  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < mn; i += (long)gridDim.x * blockDim.x) {
+    float s = 0.f;
+    for (int z = 0; z < S; z++) s += P[z * mn + i];
+    const long o = (i / N) * ldc + i % N;
+    C[o] = accumulate ? C[o] + s : s;
+  }
 }
 
 __global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y, long n) {
@@ -164,7 +199,34 @@ hipError_t mlp_gemm(const uint16_t *A, const uint16_t *B, float *C, int M, int N
                     long sbk, long sbn, int ldc, int accumulate, hipStream_t s) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
   dim3 g((N + GT - 1) / GT, (M + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm_bf16, g, dim3(256), 0, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate);
+  hipLaunchKernelGGL(k_gemm_bf16, g, dim3(256), 0, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, K, 0L);
+  return hipGetLastError();
+}
+
+static int blocks_for(long n);
+
+int mlp_splitk_slices(int M, int N, int K) {
+  const int tiles = ((N + GT - 1) / GT) * ((M + GT - 1) / GT);
+  if (tiles >= 64 || K < 512) return 1;
+  int S = 128 / tiles;
+  if (S > K / 256) S = K / 256;
+  if (S > MLP_SPLITK_MAX) S = MLP_SPLITK_MAX;
+  return S < 1 ? 1 : S;
+}
+
+hipError_t mlp_gemm_splitk(const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K, long sam, long sak,
+                           long sbk, long sbn, int ldc, int accumulate, float *partial, hipStream_t s) {
+  if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
+  const int S = mlp_splitk_slices(M, N, K);
+  if (S <= 1 || !partial) return mlp_gemm(A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, s);
+  // depth per slice, a multiple of the MFMA depth; every slice is non-empty
+  const int kc = ((K + S - 1) / S + GK - 1) / GK * GK;
+  const int Sr = (K + kc - 1) / kc;
+  dim3 g((N + GT - 1) / GT, (M + GT - 1) / GT, Sr);
+  hipLaunchKernelGGL(k_gemm_bf16, g, dim3(256), 0, s, A, B, partial, M, N, K, sam, sak, sbk, sbn, N, 0, kc,
+                     (long)M * N);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(blocks_for((long)M * N)), dim3(256), 0, s, partial, C, M, N, Sr, ldc,
+                     accumulate);
   return hipGetLastError();
 }
 
@@ -189,7 +251,7 @@ hipError_t mlp_mse(const float *Y, const float *T, uint16_t *dYb, float *dYf, do
 }
 
 hipError_t mlp_colsum(const float *dZ, float *db, int M, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((N + 255) / 256), dim3(256), 0, s, dZ, db, M, N);
+  hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(1024), 0, s, dZ, db, M, N);
   return hipGetLastError();
 }
 

@@ -31,3 +31,11 @@ def test_dominant_kernel_and_its_share(prec):
     s = 8 if prec == 0 else 4
     assert r["algorithmic_bytes_per_launch"] == 3 * s * nodes
     assert r["achieved"] == pytest.approx(3 * s * nodes / 0.006e-3 / 1e9, rel=1e-3)
+
+
+def test_mlp_flops_per_step():
+    # 10 -> 256 -> 256 -> 256 -> 256 -> 640 at batch 2: forward + weight gradient for every
+    # layer, input gradient for all but the first
+    macs = [10 * 256, 256 * 256, 256 * 256, 256 * 256, 256 * 640]
+    want = 2 * 2 * (2 * macs[0] + 3 * sum(macs[1:]))
+    assert bench.mlp_flops_per_step(2) == want
