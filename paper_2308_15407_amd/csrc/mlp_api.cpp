@@ -75,7 +75,7 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
   char *pdzb = take(2 * (size_t)maxb * maxw), *pdzf = take(4 * (size_t)maxb * maxw), *pdh = take(4 * (size_t)maxb * maxw);
   char *ppart = take(8 * 256), *ploss = take(8);
   long maxio = 0;
-  for (int l = 0; l < L; l++) maxio = std::max(maxio, (long)din[l] * dout[l]);
+  for (int l = 0; l < L; l++) maxio = std::max(maxio, std::max((long)din[l] * dout[l], (long)dout[l]));
   char *pksp = take(4 * (size_t)MLP_SPLITK_MAX * maxio);
   if (c) {
     c->nin = nin; c->width = w; c->depth = depth; c->nout = nout; c->maxb = maxb; c->L = L;
@@ -179,7 +179,7 @@ static int backward(fdlb_mlp h, const float *t_dev, int M) {
     const int in = h->din[l], out = h->dout[l];
     // dW = dZ^T H_l : A(o, m) = dZ[m][o], B(m, i) = H_l[m][i]
     MCHK(mlp_gemm_splitk(h->dZb, h->H[l], h->g + h->woff[l], out, in, M, 1, out, in, 1, in, 0, h->ksp, h->s));
-    MCHK(mlp_colsum(h->dZf, h->g + h->boff[l], M, out, h->s));
+    MCHK(mlp_colsum(h->dZf, h->g + h->boff[l], M, out, h->ksp, h->s));
     if (l > 0) {
       // dH = dZ W_l : A = dZ [M x out], B(o, i) = W_l[o][i]
       MCHK(mlp_gemm(h->dZb, h->wb + h->wboff[l], h->dH, M, in, out, out, 1, in, 1, in, 0, h->s));

@@ -18,7 +18,8 @@ hipError_t mlp_bias_act(float *Z, const float *b, uint16_t *H, int M, int N, int
 hipError_t mlp_gelu_bwd(const float *dH, const float *Z, uint16_t *dZb, float *dZf, long n, hipStream_t s);
 hipError_t mlp_mse(const float *Y, const float *T, uint16_t *dYb, float *dYf, double *part, long n, float *loss,
                    hipStream_t s);
-hipError_t mlp_colsum(const float *dZ, float *db, int M, int N, hipStream_t s);
+// db[n] = sum_m dZ[m][n], in row slices through `partial` (at least MLP_SPLITK_MAX x N floats)
+hipError_t mlp_colsum(const float *dZ, float *db, int M, int N, float *partial, hipStream_t s);
 hipError_t mlp_to_bf16(const float *x, uint16_t *y, long n, hipStream_t s);
 hipError_t mlp_adamw(float *p, float *m, float *v, const float *g, long n, float lr, float b1, float b2, float eps,
                      float wd, float c1, float c2, const long *wmap, uint16_t *wb, hipStream_t s);

@@ -5,7 +5,9 @@
 // GEMM: C[M,N] (fp32) = A[M,K] * B[K,N] (+ C if accumulate), A and B in BF16
 // with arbitrary element strides, on v_mfma_f32_16x16x16_bf16 tiles: a 256-thread
 // block owns a 64x64 tile of C (each wave a 32x32 quarter as 2x2 MFMA tiles);
-// A and B tiles of depth 16 are staged in LDS with k contiguous.
+// large products take 128x128 tiles (each wave 64x64 as 4x4 MFMA tiles); A and
+// B tiles of depth 32 are staged in two LDS buffers with k contiguous, read
+// from global memory with 16-byte loads along whichever index is contiguous.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -25,55 +27,204 @@ __device__ __forceinline__ uint16_t f2bf(float f) {
 __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
 constexpr int GT = 64;   // C tile edge
-constexpr int GK = 16;   // depth per MFMA step
+constexpr int GK = 32;   // depth per staged step (two MFMA depths of 16)
+constexpr int GP = GK + 8;   // LDS row pitch in elements (80 B: 16-byte aligned rows)
 
-__global__ void __launch_bounds__(256) k_gemm_bf16(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
+// How one operand tile (64 rows of the outer index o = m or n, GK of depth k)
+// is read from global memory: KVEC, eight consecutive k per 16-byte load (k
+// contiguous, row stride a multiple of 8); OVEC, eight consecutive o per
+// 16-byte load (o contiguous); SCALAR, one element per load (any strides).
+enum { LD_KVEC = 0, LD_OVEC = 1, LD_SCALAR = 2 };
+
+// element (o, k) of an operand with strides (so, sk); zero outside [0, no) x [kb, ke)
+__device__ __forceinline__ uint16_t ld1(const uint16_t *X, long so, long sk, int o, int k, int no, int ke) {
+  return (o < no && k < ke) ? X[(long)o * so + (long)k * sk] : (uint16_t)0;
+}
+
+__device__ __forceinline__ uint4 pack8(const uint16_t (&e)[8]) {
+  uint4 v;
+  v.x = e[0] | ((uint32_t)e[1] << 16); v.y = e[2] | ((uint32_t)e[3] << 16);
+  v.z = e[4] | ((uint32_t)e[5] << 16); v.w = e[6] | ((uint32_t)e[7] << 16);
+  return v;
+}
+
+// A thread's share of a TM x GK operand tile (TM = 64 or 128 rows of the outer
+// index o = m or n): NU units of eight elements.  Unit u = tid + 256 q is,
+// for KVEC, row u / 4 and depths (u % 4) * 8 .. +7; for OVEC, depth
+// u / (TM / 8) and rows (u % (TM / 8)) * 8 .. +7; for SCALAR, the elements
+// tid + 256 (8 q + j), j < 8, of the row-major TM x GK tile.
+template <int TM>
+struct Stage {
+  static constexpr int NU = TM / 64;
+  uint4 v[NU];
+};
+
+template <int TM, int mode>
+__device__ __forceinline__ void stage_load(Stage<TM> &st, const uint16_t *X, long so, long sk, int o0, int k0,
+                                           int no, int ke, int tid) {
+#pragma unroll
+  for (int q = 0; q < Stage<TM>::NU; q++) {
+    const int u = tid + 256 * q;
+    uint16_t e[8];
+    if constexpr (mode == LD_KVEC) {
+      const int o = o0 + (u >> 2), k = k0 + (u & 3) * 8;
+      if (o < no && k + 8 <= ke) {
+        st.v[q] = *(const uint4 *)(X + (long)o * so + k);
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) e[j] = ld1(X, so, sk, o, k + j, no, ke);
+    } else if constexpr (mode == LD_OVEC) {
+      const int k = k0 + u / (TM / 8), o = o0 + (u % (TM / 8)) * 8;
+      if (k < ke && o + 8 <= no) {
+        st.v[q] = *(const uint4 *)(X + (long)k * sk + o);
+        continue;
+      }
+#pragma unroll
+      for (int j = 0; j < 8; j++) e[j] = ld1(X, so, sk, o + j, k, no, ke);
+    } else {
+      // element idx = tid + 256 (8 q + j) of the row-major TM x GK tile
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int idx = tid + 256 * (8 * q + j);
+        e[j] = ld1(X, so, sk, o0 + idx / GK, k0 + idx % GK, no, ke);
+      }
+    }
+    st.v[q] = pack8(e);
+  }
+}
+
+// sX[o][k] (pitch GP) from a thread's staged units
+template <int TM, int mode>
+__device__ __forceinline__ void stage_store(const Stage<TM> &st, uint16_t *sX, int tid) {
+#pragma unroll
+  for (int q = 0; q < Stage<TM>::NU; q++) {
+    const int u = tid + 256 * q;
+    if constexpr (mode == LD_KVEC) {
+      *(uint4 *)(sX + (u >> 2) * GP + (u & 3) * 8) = st.v[q];
+      continue;
+    }
+    const uint4 v = st.v[q];
+    const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y, (uint16_t)(v.y >> 16),
+                           (uint16_t)v.z, (uint16_t)(v.z >> 16), (uint16_t)v.w, (uint16_t)(v.w >> 16)};
+    if constexpr (mode == LD_OVEC) {
+      const int k = u / (TM / 8), o = (u % (TM / 8)) * 8;
+#pragma unroll
+      for (int j = 0; j < 8; j++) sX[(o + j) * GP + k] = e[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < 8; j++) {
+        const int idx = tid + 256 * (8 * q + j);
+        sX[(idx / GK) * GP + idx % GK] = e[j];
+      }
+    }
+  }
+}
+
+// A 256-thread block owns a TM x TM tile of C (TM = 64 or 128; each wave a
+// TM/2 x TM/2 quarter as (TM/32)^2 MFMA tiles of 16 x 16).  Depth steps of
+// GK are staged through two LDS buffers: the global loads of step s+1 are in
+// flight while step s is multiplied, and one barrier per step separates a
+// buffer's reads from its next writes.  Split K: block z takes depths
+// [z kchunk, (z+1) kchunk) and writes slice z of C.
+template <int TM, int AM, int BM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 128 ? 2 : 1, 8))) k_gemm_bf16(const uint16_t *__restrict__ A, const uint16_t *__restrict__ B,
                                                    float *__restrict__ C, int M, int N, int K, long sam, long sak,
                                                    long sbk, long sbn, int ldc, int accumulate, int kchunk,
                                                    long cslice) {
-  __shared__ uint16_t sA[GT][GK + 4];   // [m][k]
-  __shared__ uint16_t sB[GT][GK + 4];   // [n][k]
+  constexpr int IT = TM / 32;   // MFMA tiles per wave and dimension
+  __shared__ __attribute__((aligned(16))) uint16_t sA[2][TM * GP];   // [m][k]
+  __shared__ __attribute__((aligned(16))) uint16_t sB[2][TM * GP];   // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int m0 = blockIdx.y * GT, n0 = blockIdx.x * GT;
-  // split K: block z takes depths [kb, ke) and writes its own slice of C
+  const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
   const int kb = blockIdx.z * kchunk, ke = min(K, kb + kchunk);
   C += blockIdx.z * cslice;
   const int wr = wv >> 1, wc = wv & 1;
-  v4f acc[2][2];
-  for (int i = 0; i < 2; i++)
-    for (int j = 0; j < 2; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+  v4f acc[IT][IT];
+#pragma unroll
+  for (int i = 0; i < IT; i++)
+#pragma unroll
+    for (int j = 0; j < IT; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+  Stage<TM> sa, sb;
+  stage_load<TM, AM>(sa, A, sam, sak, m0, kb, M, ke, tid);
+  stage_load<TM, BM>(sb, B, sbn, sbk, n0, kb, N, ke, tid);
+  stage_store<TM, AM>(sa, sA[0], tid);
+  stage_store<TM, BM>(sb, sB[0], tid);
+  __syncthreads();
+  const int row = lane & 15, kq = (lane >> 4) * 4;
+  int buf = 0;
   for (int k0 = kb; k0 < ke; k0 += GK) {
-    // stage: 64x16 elements of A and of B, 4 per thread each
-    for (int e = tid; e < GT * GK; e += 256) {
-      const int r = e / GK, kk = e % GK;
-      const int gm = m0 + r, gn = n0 + r, gk = k0 + kk;
-      sA[r][kk] = (gm < M && gk < ke) ? A[(long)gm * sam + (long)gk * sak] : (uint16_t)0;
-      sB[r][kk] = (gn < N && gk < ke) ? B[(long)gk * sbk + (long)gn * sbn] : (uint16_t)0;
+    const bool more = k0 + GK < ke;
+    if (more) {
+      stage_load<TM, AM>(sa, A, sam, sak, m0, k0 + GK, M, ke, tid);
+      stage_load<TM, BM>(sb, B, sbn, sbk, n0, k0 + GK, N, ke, tid);
+    }
+#pragma unroll
+    for (int ks = 0; ks < GK; ks += 16) {
+      v4s a[IT], b[IT];
+#pragma unroll
+      for (int i = 0; i < IT; i++) {
+        a[i] = *(const v4s *)(sA[buf] + (wr * (TM / 2) + i * 16 + row) * GP + ks + kq);
+        b[i] = *(const v4s *)(sB[buf] + (wc * (TM / 2) + i * 16 + row) * GP + ks + kq);
+      }
+#pragma unroll
+      for (int i = 0; i < IT; i++)
+#pragma unroll
+        for (int j = 0; j < IT; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    }
+    if (more) {
+      stage_store<TM, AM>(sa, sA[buf ^ 1], tid);
+      stage_store<TM, BM>(sb, sB[buf ^ 1], tid);
     }
     __syncthreads();
-    const int row = lane & 15, kq = (lane >> 4) * 4;
-    v4s a[2], b[2];
-    for (int i = 0; i < 2; i++) {
-      const uint16_t *pa = &sA[wr * 32 + i * 16 + row][kq];
-      a[i] = (v4s){(short)pa[0], (short)pa[1], (short)pa[2], (short)pa[3]};
-      const uint16_t *pb = &sB[wc * 32 + i * 16 + row][kq];
-      b[i] = (v4s){(short)pb[0], (short)pb[1], (short)pb[2], (short)pb[3]};
-    }
-    for (int i = 0; i < 2; i++)
-      for (int j = 0; j < 2; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
-    __syncthreads();
+    buf ^= 1;
   }
   // D layout: lane l holds column l%16, rows 4*(l/16)+t
   const int col = lane & 15, rq = (lane >> 4) * 4;
-  for (int i = 0; i < 2; i++)
-    for (int j = 0; j < 2; j++)
+#pragma unroll
+  for (int i = 0; i < IT; i++)
+#pragma unroll
+    for (int j = 0; j < IT; j++)
+#pragma unroll
       for (int t = 0; t < 4; t++) {
-        const int gm = m0 + wr * 32 + i * 16 + rq + t, gn = n0 + wc * 32 + j * 16 + col;
+        const int gm = m0 + wr * (TM / 2) + i * 16 + rq + t, gn = n0 + wc * (TM / 2) + j * 16 + col;
         if (gm < M && gn < N) {
           float *p = &C[(long)gm * ldc + gn];
           *p = accumulate ? *p + acc[i][j][t] : acc[i][j][t];
         }
       }
+}
+
+// launch k_gemm_bf16<TM, AM, BM> for the run-time read modes of A and B
+template <int TM, int AM>
+static void launch_b(int bm, dim3 g, hipStream_t s, const uint16_t *A, const uint16_t *B, float *C, int M, int N,
+                     int K, long sam, long sak, long sbk, long sbn, int ldc, int accumulate, int kchunk, long cslice) {
+  if (bm == LD_KVEC)
+    hipLaunchKernelGGL((k_gemm_bf16<TM, AM, LD_KVEC>), g, dim3(256), 0, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc,
+                       accumulate, kchunk, cslice);
+  else if (bm == LD_OVEC)
+    hipLaunchKernelGGL((k_gemm_bf16<TM, AM, LD_OVEC>), g, dim3(256), 0, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc,
+                       accumulate, kchunk, cslice);
+  else
+    hipLaunchKernelGGL((k_gemm_bf16<TM, AM, LD_SCALAR>), g, dim3(256), 0, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc,
+                       accumulate, kchunk, cslice);
+}
+
+template <int TM>
+static void launch_gemm(int am, int bm, dim3 g, hipStream_t s, const uint16_t *A, const uint16_t *B, float *C, int M,
+                        int N, int K, long sam, long sak, long sbk, long sbn, int ldc, int accumulate, int kchunk,
+                        long cslice) {
+  if (am == LD_KVEC) launch_b<TM, LD_KVEC>(bm, g, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, kchunk, cslice);
+  else if (am == LD_OVEC) launch_b<TM, LD_OVEC>(bm, g, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, kchunk, cslice);
+  else launch_b<TM, LD_SCALAR>(bm, g, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, kchunk, cslice);
+}
+
+// read mode of an operand with outer stride so and depth stride sk
+static int ld_mode(const uint16_t *X, long so, long sk) {
+  const bool al = ((uintptr_t)X & 15) == 0;
+  if (al && sk == 1 && so % 8 == 0) return LD_KVEC;
+  if (al && so == 1 && sk % 8 == 0) return LD_OVEC;
+  return LD_SCALAR;
 }
 
 __device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
@@ -124,40 +275,45 @@ __global__ void __launch_bounds__(256) k_mse(const float *__restrict__ Y, const 
   if (threadIdx.x == 0) part[blockIdx.x] = red[0];
 }
 
+// loss = sum of the block partials / n: one wave, lane l adds partials l, l + 64,
+// ...; the lane sums are then added in lane order by lane 0 from LDS (fixed order)
 __global__ void k_sum_parts(const double *__restrict__ part, int nparts, long n, float *__restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0;
-    for (int i = 0; i < nparts; i++) s += part[i];
-    *out = (float)(s / (double)n);
+  __shared__ double red[64];
+  const int l = threadIdx.x;
+  double s = 0;
+  for (int i = l; i < nparts; i += 64) s += part[i];
+  red[l] = s;
+  __syncthreads();
+  if (l == 0) {
+    double t = 0;
+    for (int i = 0; i < 64; i++) t += red[i];
+    *out = (float)(t / (double)n);
   }
 }
 
-// db[n] = sum_m dZ[m][n]: a 1024-thread block per 64 columns; wave w sums rows
-// w, w + 16, ... of its lane's column in four interleaved partial sums (loads
-// coalesced along the row), then the 16 wave sums are added in wave order
-// (a fixed order: the result does not depend on timing)
-__global__ void __launch_bounds__(1024) k_colsum(const float *__restrict__ dZ, float *__restrict__ db, int M, int N) {
-  __shared__ float red[16][64];
+// Partial column sums of dZ[M][N]: block (x, y) adds rows y R .. y R + R - 1
+// of columns 64 x .. 64 x + 63 (R = ceil(M / gridDim.y)); wave w takes rows
+// w, w + 4, ... of the slice in two interleaved sums, and the four wave sums
+// are added in wave order into part[y][n] (a fixed order: the result does not
+// depend on timing).  k_splitk_sum then adds the slices in order.
+__global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ dZ, float *__restrict__ part, int M,
+                                                     int N) {
+  __shared__ float red[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int n = blockIdx.x * 64 + lane;
-  float s0 = 0.f, s1 = 0.f, s2 = 0.f, s3 = 0.f;
+  const int R = (M + gridDim.y - 1) / gridDim.y, r0 = blockIdx.y * R, r1 = min(M, r0 + R);
+  float s0 = 0.f, s1 = 0.f;
   if (n < N) {
-    int m = wv;
-    for (; m + 48 < M; m += 64) {
+    int m = r0 + wv;
+    for (; m + 4 < r1; m += 8) {
       s0 += dZ[(long)m * N + n];
-      s1 += dZ[(long)(m + 16) * N + n];
-      s2 += dZ[(long)(m + 32) * N + n];
-      s3 += dZ[(long)(m + 48) * N + n];
+      s1 += dZ[(long)(m + 4) * N + n];
     }
-    for (; m < M; m += 16) s0 += dZ[(long)m * N + n];
+    for (; m < r1; m += 4) s0 += dZ[(long)m * N + n];
   }
-  red[wv][lane] = (s0 + s1) + (s2 + s3);
+  red[wv][lane] = s0 + s1;
   __syncthreads();
-  if (wv == 0 && n < N) {
-    float s = 0.f;
-    for (int w = 0; w < 16; w++) s += red[w][lane];
-    db[n] = s;
-  }
+  if (wv == 0 && n < N) part[(long)blockIdx.y * N + n] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
 // C[m][n] (ldc) (+)= sum over z of P[z][m][n] (slices of M x N), in z order
@@ -198,8 +354,15 @@ __global__ void k_adamw(float *__restrict__ p, float *__restrict__ m, float *__r
 hipError_t mlp_gemm(const uint16_t *A, const uint16_t *B, float *C, int M, int N, int K, long sam, long sak,
                     long sbk, long sbn, int ldc, int accumulate, hipStream_t s) {
   if (M <= 0 || N <= 0 || K <= 0) return hipSuccess;
-  dim3 g((N + GT - 1) / GT, (M + GT - 1) / GT);
-  hipLaunchKernelGGL(k_gemm_bf16, g, dim3(256), 0, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, K, 0L);
+  const int am = ld_mode(A, sam, sak), bm = ld_mode(B, sbn, sbk);
+  // 128 x 128 tiles where they still give at least one block per CU
+  if ((long)((M + 127) / 128) * ((N + 127) / 128) >= 256) {
+    dim3 g((N + 127) / 128, (M + 127) / 128);
+    launch_gemm<128>(am, bm, g, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, K, 0L);
+  } else {
+    dim3 g((N + GT - 1) / GT, (M + GT - 1) / GT);
+    launch_gemm<GT>(am, bm, g, s, A, B, C, M, N, K, sam, sak, sbk, sbn, ldc, accumulate, K, 0L);
+  }
   return hipGetLastError();
 }
 
@@ -223,8 +386,8 @@ hipError_t mlp_gemm_splitk(const uint16_t *A, const uint16_t *B, float *C, int M
   const int kc = ((K + S - 1) / S + GK - 1) / GK * GK;
   const int Sr = (K + kc - 1) / kc;
   dim3 g((N + GT - 1) / GT, (M + GT - 1) / GT, Sr);
-  hipLaunchKernelGGL(k_gemm_bf16, g, dim3(256), 0, s, A, B, partial, M, N, K, sam, sak, sbk, sbn, N, 0, kc,
-                     (long)M * N);
+  launch_gemm<GT>(ld_mode(A, sam, sak), ld_mode(B, sbn, sbk), g, s, A, B, partial, M, N, K, sam, sak, sbk, sbn, N, 0, kc,
+                  (long)M * N);
   hipLaunchKernelGGL(k_splitk_sum, dim3(blocks_for((long)M * N)), dim3(256), 0, s, partial, C, M, N, Sr, ldc,
                      accumulate);
   return hipGetLastError();
@@ -250,8 +413,13 @@ hipError_t mlp_mse(const float *Y, const float *T, uint16_t *dYb, float *dYf, do
   return hipGetLastError();
 }
 
-hipError_t mlp_colsum(const float *dZ, float *db, int M, int N, hipStream_t s) {
-  hipLaunchKernelGGL(k_colsum, dim3((N + 63) / 64), dim3(1024), 0, s, dZ, db, M, N);
+hipError_t mlp_colsum(const float *dZ, float *db, int M, int N, float *partial, hipStream_t s) {
+  // row slices of at least 64 rows, at most MLP_SPLITK_MAX of them (partial holds slices x N)
+  int S = M / 64;
+  if (S > MLP_SPLITK_MAX) S = MLP_SPLITK_MAX;
+  if (S < 1) S = 1;
+  hipLaunchKernelGGL(k_colsum_part, dim3((N + 63) / 64, S), dim3(256), 0, s, dZ, partial, M, N);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(blocks_for(N)), dim3(256), 0, s, partial, db, 1, N, S, N, 0);
   return hipGetLastError();
 }
 

@@ -20,8 +20,15 @@ def bf16_bits(a):
     return ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
 
 
+# strides that are not multiples of 8 take the scalar loads; (200, 136, 72) and
+# (64, 128, 40) read A and B with 16-byte loads along k, (96, 256, 264) along
+# m and n, with ragged tile and depth edges; the two largest take the 128 x 128
+# tiles (at least 256 of them)
 @pytest.mark.parametrize("M,N,K,ta,tb", [(70, 45, 37, False, False), (64, 64, 16, True, False),
-                                          (130, 20, 100, False, True), (5, 300, 3, True, True)])
+                                          (130, 20, 100, False, True), (5, 300, 3, True, True),
+                                          (200, 136, 72, False, False), (96, 256, 264, True, False),
+                                          (64, 128, 40, False, True), (96, 256, 264, True, True),
+                                          (2100, 2060, 72, False, False), (2048, 2100, 40, True, True)])
 def test_gemm_bf16_layout_and_values(M, N, K, ta, tb):
     import torch
     from paper_2308_15407_amd import fdlb as F
