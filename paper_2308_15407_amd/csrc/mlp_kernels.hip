@@ -50,9 +50,11 @@ __device__ __forceinline__ uint4 pack8(const uint16_t (&e)[8]) {
 
 // A thread's share of a TM x GK operand tile (TM = 64 or 128 rows of the outer
 // index o = m or n): NU units of eight elements.  Unit u = tid + 256 q is,
-// for KVEC, row u / 4 and depths (u % 4) * 8 .. +7; for OVEC, depth
-// u / (TM / 8) and rows (u % (TM / 8)) * 8 .. +7; for SCALAR, the elements
-// tid + 256 (8 q + j), j < 8, of the row-major TM x GK tile.
+// for KVEC, row u / 4 and depths (u % 4) * 8 .. +7; for OVEC, depth u % GK
+// and rows (u / GK) * 8 .. +7 (depth fastest across lanes: the transposing
+// 2-byte LDS stores of 32 lanes then fall in consecutive words instead of two
+// banks); for SCALAR, the elements tid + 256 (8 q + j), j < 8, of the
+// row-major TM x GK tile.
 template <int TM>
 struct Stage {
   static constexpr int NU = TM / 64;
@@ -75,7 +77,7 @@ __device__ __forceinline__ void stage_load(Stage<TM> &st, const uint16_t *X, lon
 #pragma unroll
       for (int j = 0; j < 8; j++) e[j] = ld1(X, so, sk, o, k + j, no, ke);
     } else if constexpr (mode == LD_OVEC) {
-      const int k = k0 + u / (TM / 8), o = o0 + (u % (TM / 8)) * 8;
+      const int k = k0 + u % GK, o = o0 + (u / GK) * 8;
       if (k < ke && o + 8 <= no) {
         st.v[q] = *(const uint4 *)(X + (long)k * sk + o);
         continue;
@@ -108,7 +110,7 @@ __device__ __forceinline__ void stage_store(const Stage<TM> &st, uint16_t *sX, i
     const uint16_t e[8] = {(uint16_t)v.x, (uint16_t)(v.x >> 16), (uint16_t)v.y, (uint16_t)(v.y >> 16),
                            (uint16_t)v.z, (uint16_t)(v.z >> 16), (uint16_t)v.w, (uint16_t)(v.w >> 16)};
     if constexpr (mode == LD_OVEC) {
-      const int k = u / (TM / 8), o = (u % (TM / 8)) * 8;
+      const int k = u % GK, o = (u / GK) * 8;
 #pragma unroll
       for (int j = 0; j < 8; j++) sX[(o + j) * GP + k] = e[j];
     } else {
