@@ -3,11 +3,12 @@
 // accumulation, FP32 master weights and AdamW.
 //
 // GEMM: C[M,N] (fp32) = A[M,K] * B[K,N] (+ C if accumulate), A and B in BF16
-// with arbitrary element strides, on v_mfma_f32_16x16x16_bf16 tiles: a 256-thread
-// block owns a 64x64 tile of C (each wave a 32x32 quarter as 2x2 MFMA tiles);
-// large products take 128x128 tiles (each wave 64x64 as 4x4 MFMA tiles); A and
-// B tiles of depth 32 are staged in two LDS buffers with k contiguous, read
-// from global memory with 16-byte loads along whichever index is contiguous.
+// with arbitrary element strides.  A 256-thread block owns a 64x64 tile of C
+// (each wave a 32x32 quarter as 2x2 tiles of v_mfma_f32_16x16x16_bf16), or a
+// 128x128 tile for large products (each wave 64x64 as 2x2 tiles of
+// v_mfma_f32_32x32x16_bf16).  A and B tiles of depth 32 are staged in two LDS
+// buffers with k contiguous, read from global memory with 16-byte loads along
+// whichever index is contiguous.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -17,6 +18,8 @@ namespace fdlb {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
+typedef float v16f __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t f2bf(float f) {
   uint32_t u = __float_as_uint(f);
@@ -124,7 +127,7 @@ __device__ __forceinline__ void stage_store(const Stage<TM> &st, uint16_t *sX, i
 }
 
 // A 256-thread block owns a TM x TM tile of C (TM = 64 or 128; each wave a
-// TM/2 x TM/2 quarter as (TM/32)^2 MFMA tiles of 16 x 16).  Depth steps of
+// TM/2 x TM/2 quarter as 2 x 2 MFMA tiles of 16 x 16 or 32 x 32).  Depth steps of
 // GK are staged through two LDS buffers: the global loads of step s+1 are in
 // flight while step s is multiplied, and one barrier per step separates a
 // buffer's reads from its next writes.  Split K: block z takes depths
@@ -134,7 +137,11 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 
                                                    float *__restrict__ C, int M, int N, int K, long sam, long sak,
                                                    long sbk, long sbn, int ldc, int accumulate, int kchunk,
                                                    long cslice) {
-  constexpr int IT = TM / 32;   // MFMA tiles per wave and dimension
+  // TM = 64: each wave 2 x 2 MFMA tiles of 16 x 16 (v_mfma_f32_16x16x16_bf16);
+  // TM = 128: each wave 2 x 2 tiles of 32 x 32 (v_mfma_f32_32x32x16_bf16: lane l
+  // supplies rows or columns l % 32 at depths 8 (l / 32) .. +7)
+  constexpr bool BIG = TM == 128;
+  constexpr int IT = 2;
   __shared__ __attribute__((aligned(16))) uint16_t sA[2][TM * GP];   // [m][k]
   __shared__ __attribute__((aligned(16))) uint16_t sB[2][TM * GP];   // [n][k]
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -143,10 +150,14 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 
   C += blockIdx.z * cslice;
   const int wr = wv >> 1, wc = wv & 1;
   v4f acc[IT][IT];
+  v16f acc32[IT][IT];
 #pragma unroll
   for (int i = 0; i < IT; i++)
 #pragma unroll
-    for (int j = 0; j < IT; j++) acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < IT; j++) {
+      if constexpr (BIG) acc32[i][j] = (v16f){0.f};
+      else acc[i][j] = (v4f){0.f, 0.f, 0.f, 0.f};
+    }
   Stage<TM> sa, sb;
   stage_load<TM, AM>(sa, A, sam, sak, m0, kb, M, ke, tid);
   stage_load<TM, BM>(sb, B, sbn, sbk, n0, kb, N, ke, tid);
@@ -163,16 +174,30 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 
     }
 #pragma unroll
     for (int ks = 0; ks < GK; ks += 16) {
-      v4s a[IT], b[IT];
+      if constexpr (BIG) {
+        const int r32 = lane & 31, k8 = (lane >> 5) * 8;
+        v8bf a[IT], b[IT];
 #pragma unroll
-      for (int i = 0; i < IT; i++) {
-        a[i] = *(const v4s *)(sA[buf] + (wr * (TM / 2) + i * 16 + row) * GP + ks + kq);
-        b[i] = *(const v4s *)(sB[buf] + (wc * (TM / 2) + i * 16 + row) * GP + ks + kq);
+        for (int i = 0; i < IT; i++) {
+          a[i] = *(const v8bf *)(sA[buf] + (wr * 64 + i * 32 + r32) * GP + ks + k8);
+          b[i] = *(const v8bf *)(sB[buf] + (wc * 64 + i * 32 + r32) * GP + ks + k8);
+        }
+#pragma unroll
+        for (int i = 0; i < IT; i++)
+#pragma unroll
+          for (int j = 0; j < IT; j++) acc32[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[i], b[j], acc32[i][j], 0, 0, 0);
+      } else {
+        v4s a[IT], b[IT];
+#pragma unroll
+        for (int i = 0; i < IT; i++) {
+          a[i] = *(const v4s *)(sA[buf] + (wr * 32 + i * 16 + row) * GP + ks + kq);
+          b[i] = *(const v4s *)(sB[buf] + (wc * 32 + i * 16 + row) * GP + ks + kq);
+        }
+#pragma unroll
+        for (int i = 0; i < IT; i++)
+#pragma unroll
+          for (int j = 0; j < IT; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
       }
-#pragma unroll
-      for (int i = 0; i < IT; i++)
-#pragma unroll
-        for (int j = 0; j < IT; j++) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
     }
     if (more) {
       stage_store<TM, AM>(sa, sA[buf ^ 1], tid);
@@ -181,20 +206,37 @@ __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(TM == 
     __syncthreads();
     buf ^= 1;
   }
-  // D layout: lane l holds column l%16, rows 4*(l/16)+t
-  const int col = lane & 15, rq = (lane >> 4) * 4;
+  if constexpr (BIG) {
+    // 32 x 32 D layout: lane l holds column l%32, value 4g+t at row 8g + 4(l/32) + t
+    const int col = lane & 31, rh = (lane >> 5) * 4;
 #pragma unroll
-  for (int i = 0; i < IT; i++)
+    for (int i = 0; i < IT; i++)
 #pragma unroll
-    for (int j = 0; j < IT; j++)
+      for (int j = 0; j < IT; j++)
 #pragma unroll
-      for (int t = 0; t < 4; t++) {
-        const int gm = m0 + wr * (TM / 2) + i * 16 + rq + t, gn = n0 + wc * (TM / 2) + j * 16 + col;
-        if (gm < M && gn < N) {
-          float *p = &C[(long)gm * ldc + gn];
-          *p = accumulate ? *p + acc[i][j][t] : acc[i][j][t];
+        for (int v = 0; v < 16; v++) {
+          const int gm = m0 + wr * 64 + i * 32 + 8 * (v >> 2) + rh + (v & 3), gn = n0 + wc * 64 + j * 32 + col;
+          if (gm < M && gn < N) {
+            float *p = &C[(long)gm * ldc + gn];
+            *p = accumulate ? *p + acc32[i][j][v] : acc32[i][j][v];
+          }
         }
-      }
+  } else {
+    // 16 x 16 D layout: lane l holds column l%16, rows 4*(l/16)+t
+    const int col = lane & 15, rq = (lane >> 4) * 4;
+#pragma unroll
+    for (int i = 0; i < IT; i++)
+#pragma unroll
+      for (int j = 0; j < IT; j++)
+#pragma unroll
+        for (int t = 0; t < 4; t++) {
+          const int gm = m0 + wr * 32 + i * 16 + rq + t, gn = n0 + wc * 32 + j * 16 + col;
+          if (gm < M && gn < N) {
+            float *p = &C[(long)gm * ldc + gn];
+            *p = accumulate ? *p + acc[i][j][t] : acc[i][j][t];
+          }
+        }
+  }
 }
 
 // launch k_gemm_bf16<TM, AM, BM> for the run-time read modes of A and B
