@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--workload", default="C3", choices=sorted(WORKLOADS))
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
     ap.add_argument("--no-extra", action="store_true", help="only the main workload")
+    ap.add_argument("--no-pmc", action="store_true", help="skip the counter passes of the headline kernel")
     ap.add_argument("--large-steps", type=int, default=60)
     ap.add_argument("--retune", action="store_true")
     ap.add_argument("--sweep-steps", type=int, default=100)
@@ -86,6 +87,65 @@ def read_traffic(kernel, workload):
                 return None
             return float(parts[4]) + float(parts[5])
     return None
+
+
+def measure_traffic(workload, prec, tile, timeout_s=150):
+    """HBM bytes per launch of the stage-2 update, measured in this run: two
+    rocprofv3 --pmc passes (FETCH_SIZE, then WRITE_SIZE, KiB per dispatch) over
+    a short child run of the same workload and tiling, each scaled by what the
+    same counter reads for a 256 MiB device copy in that child run.  Returns
+    (bytes, detail) or (None, reason) when the profiler is not usable here."""
+    import glob
+    import shutil
+    import sqlite3
+    import subprocess
+    import tempfile
+    kname = "k_update<%s, 2," % ("double" if prec == 0 else "float")
+    per = {}
+    for counter in ("FETCH_SIZE", "WRITE_SIZE"):
+        d = tempfile.mkdtemp(prefix="fdlb_pmc_", dir="/tmp")
+        try:
+            cmd = ["timeout", "-s", "KILL", str(timeout_s), "rocprofv3", "--pmc", counter, "-d", d, "-o", "pmc", "--",
+                   sys.executable, os.path.join(ROOT, "bench.py"), "--profile-case", workload, "--precision",
+                   str(prec), "--steps", "3", "--tiling", str(tile[0]), str(tile[1]), "--copy-mib", "256"]
+            env = dict(os.environ, TMPDIR="/tmp")
+            r = subprocess.run(cmd, cwd=ROOT, env=env, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+            dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
+            if r.returncode != 0 or not dbs:
+                return None, "rocprofv3 --pmc %s: exit %d, %d result files" % (counter, r.returncode, len(dbs))
+            vals = {"k": [], "copy": []}
+            con = sqlite3.connect(dbs[0])
+            for n, cn, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
+                if cn != counter:
+                    continue
+                if kname in n:
+                    vals["k"].append(v)
+                elif "k_copy_probe" in n:
+                    vals["copy"].append(v)
+            con.close()
+            if not vals["k"] or not vals["copy"]:
+                return None, "no %s samples for the update or the copy" % counter
+            kib = sum(vals["k"]) / len(vals["k"])
+            factor = 262144.0 / (sum(vals["copy"]) / len(vals["copy"]))
+            per[counter] = {"kib_per_dispatch": round(kib, 1), "copy_factor": round(factor, 4),
+                            "bytes": round(kib * factor * 1024)}
+        except (OSError, sqlite3.Error) as e:
+            return None, "rocprofv3 --pmc %s: %s" % (counter, e)
+        finally:
+            shutil.rmtree(d, ignore_errors=True)
+    return per["FETCH_SIZE"]["bytes"] + per["WRITE_SIZE"]["bytes"], per
+
+
+def attach_traffic(roof, workload, prec, tile):
+    """Replace a roofline object's traffic by the counters of measure_traffic
+    (this run); the committed profile's value stands if the profiler fails."""
+    t, detail = measure_traffic(workload, prec, tile)
+    if t is not None:
+        roof["traffic"] = t
+        roof["traffic_source"] = "rocprofv3 --pmc FETCH_SIZE, WRITE_SIZE in this run, copy-calibrated"
+        roof["traffic_counters"] = detail
+    else:
+        roof["traffic_source"] = ("committed profile (%s)" % detail) if roof["traffic"] is not None else detail
 
 
 def timed_run(solver, steps, warmup):
@@ -418,6 +478,12 @@ def main():
         "kernel_ms": {"table": round(prof[0], 5), "update": [round(x, 5) for x in prof[1:4]]},
     }
     del s
+    torch.cuda.synchronize()
+    if not args.no_pmc:
+        # the headline kernel's HBM traffic from counters taken in this run (the
+        # committed profile's value stands only if the profiler is unusable)
+        upd = out["roofline"] if out["roofline"]["kernel"].startswith("k_update") else out["roofline"]["other_kernel"]
+        attach_traffic(upd, wl, 0, tile)
     if not args.no_extra:
         cfg32 = I.config(wl, precision=1)
         s32, ms32, _, tile32, prof32 = measure(cfg32, args.steps, args.warmup, args.retune)
@@ -447,6 +513,9 @@ def main():
                 "tiling": {"kx_per_chunk": tileL[0], "waves": tileL[1]},
                 "roofline": update_roofline(profL, nodesL, prec, "R2"),
                 "kernel_ms": {"table": round(profL[0], 5), "update": [round(x, 5) for x in profL[1 + 3 * prec:4 + 3 * prec]]}}
+            if not args.no_pmc:
+                torch.cuda.synchronize()
+                attach_traffic(out["large_case_" + ("f64" if prec == 0 else "f32")]["roofline"], "R2", prec, tileL)
         out["reduced_1d"] = reduced_leg(args.large_steps, "R2")
         out["reduced_2d"] = reduced_leg(args.steps, "C2", warmup=args.warmup)
         out["sweep"] = sweep_leg(args.sweep_steps, args.retune)
