@@ -110,9 +110,10 @@ def measure_traffic(workload, prec, tile, timeout_s=150):
                    str(prec), "--steps", "3", "--tiling", str(tile[0]), str(tile[1]), "--copy-mib", "256"]
             env = dict(os.environ, TMPDIR="/tmp")
             r = subprocess.run(cmd, cwd=ROOT, env=env, stdout=subprocess.DEVNULL, stderr=subprocess.DEVNULL)
+            # the profiler can exit non-zero after a complete run; the samples decide
             dbs = glob.glob(os.path.join(d, "**", "*.db"), recursive=True)
-            if r.returncode != 0 or not dbs:
-                return None, "rocprofv3 --pmc %s: exit %d, %d result files" % (counter, r.returncode, len(dbs))
+            if not dbs:
+                return None, "rocprofv3 --pmc %s: exit %d, no result file" % (counter, r.returncode)
             vals = {"k": [], "copy": []}
             con = sqlite3.connect(dbs[0])
             for n, cn, v in con.execute("select kernel_name, counter_name, value from counters_collection"):
@@ -124,7 +125,8 @@ def measure_traffic(workload, prec, tile, timeout_s=150):
                     vals["copy"].append(v)
             con.close()
             if not vals["k"] or not vals["copy"]:
-                return None, "no %s samples for the update or the copy" % counter
+                return None, "rocprofv3 --pmc %s: exit %d, no samples for the update or the copy" % (counter,
+                                                                                                  r.returncode)
             kib = sum(vals["k"]) / len(vals["k"])
             factor = 262144.0 / (sum(vals["copy"]) / len(vals["copy"]))
             per[counter] = {"kib_per_dispatch": round(kib, 1), "copy_factor": round(factor, 4),
