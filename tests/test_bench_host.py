@@ -1,6 +1,8 @@
 """Host arithmetic of bench.py's roofline objects (no GPU): which kernel is
 priced as dominant, its share of the step's kernel time, and the algorithmic
-bytes per launch."""
+bytes per launch, and the parsing and copy calibration of the counter passes."""
+import os
+
 import pytest
 
 import bench
@@ -39,3 +41,45 @@ def test_mlp_flops_per_step():
     macs = [10 * 256, 256 * 256, 256 * 256, 256 * 256, 256 * 640]
     want = 2 * 2 * (2 * macs[0] + 3 * sum(macs[1:]))
     assert bench.mlp_flops_per_step(2) == want
+
+
+def test_measure_traffic_scales_each_counter_by_the_copy(monkeypatch):
+    """The two counter passes are parsed from the profiler's result database
+    and each is scaled by the copy kernel's reading of the same counter
+    (262144 KiB moved per copy); the profiler itself is replaced here by a
+    stand-in that writes such a database."""
+    import sqlite3
+    import subprocess
+
+    readings = {"FETCH_SIZE": (5000.0, 131072.0), "WRITE_SIZE": (3700.0, 262144.0)}
+
+    def fake_run(cmd, **kw):
+        counter = cmd[cmd.index("--pmc") + 1]
+        d = cmd[cmd.index("-d") + 1]
+        os.makedirs(os.path.join(d, "host"), exist_ok=True)
+        con = sqlite3.connect(os.path.join(d, "host", "pmc_results.db"))
+        con.execute("create table counters_collection (kernel_name text, counter_name text, value real)")
+        k, copy = readings[counter]
+        for v in (k - 10.0, k + 10.0):
+            con.execute("insert into counters_collection values (?, ?, ?)",
+                        ("void fdlb::k_update<double, 2, true, 8>(x)", counter, v))
+        con.execute("insert into counters_collection values (?, ?, ?)",
+                    ("void fdlb::k_update<double, 1, true, 8>(x)", counter, 1e9))   # another stage
+        con.execute("insert into counters_collection values (?, ?, ?)", ("fdlb::k_copy_probe(x)", counter, copy))
+        con.commit()
+        con.close()
+        return subprocess.CompletedProcess(cmd, 139)   # the profiler may exit non-zero after a full run
+
+    monkeypatch.setattr(subprocess, "run", fake_run)
+    t, detail = bench.measure_traffic("C3", 0, (2, 8))
+    fetch = 5000.0 * (262144.0 / 131072.0) * 1024
+    write = 3700.0 * (262144.0 / 262144.0) * 1024
+    assert detail["FETCH_SIZE"]["bytes"] == round(fetch) and detail["WRITE_SIZE"]["bytes"] == round(write)
+    assert t == round(fetch) + round(write)
+
+
+def test_measure_traffic_reports_a_missing_profiler(monkeypatch):
+    import subprocess
+    monkeypatch.setattr(subprocess, "run", lambda cmd, **kw: subprocess.CompletedProcess(cmd, 127))
+    t, detail = bench.measure_traffic("R2", 1, (8, 4))
+    assert t is None and "no result file" in detail
