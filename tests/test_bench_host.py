@@ -83,3 +83,15 @@ def test_measure_traffic_reports_a_missing_profiler(monkeypatch):
     monkeypatch.setattr(subprocess, "run", lambda cmd, **kw: subprocess.CompletedProcess(cmd, 127))
     t, detail = bench.measure_traffic("R2", 1, (8, 4))
     assert t is None and "no result file" in detail
+
+
+def test_more_than_one_gpu_is_refused_with_a_message():
+    """bench.py measures one GPU: any other --gpus exits 2 with a message,
+    before it touches a device."""
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], cwd=root,
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""
