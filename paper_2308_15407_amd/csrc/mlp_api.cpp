@@ -41,6 +41,7 @@ struct fdlb_mlp_ctx {
   double *part;
   float *loss;
   float *ksp;                           // split-K partial products of the weight gradients
+  long ksp_floats;                      // its size
   long t;
 };
 
@@ -73,7 +74,7 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
   ph[L] = nullptr;
   for (int l = 0; l < L; l++) pz[l] = take(4 * (size_t)maxb * dout[l]);
   char *pdzb = take(2 * (size_t)maxb * maxw), *pdzf = take(4 * (size_t)maxb * maxw), *pdh = take(4 * (size_t)maxb * maxw);
-  char *ppart = take(8 * 256), *ploss = take(8);
+  char *ppart = take(8 * (size_t)MLP_LOSS_PARTS), *ploss = take(8);
   long maxio = 0;
   for (int l = 0; l < L; l++) maxio = std::max(maxio, std::max((long)din[l] * dout[l], (long)dout[l]));
   char *pksp = take(4 * (size_t)MLP_SPLITK_MAX * maxio);
@@ -86,6 +87,7 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
     for (int l = 0; l < L; l++) { c->H[l] = (uint16_t *)ph[l]; c->Z[l] = (float *)pz[l]; }
     c->dZb = (uint16_t *)pdzb; c->dZf = (float *)pdzf; c->dH = (float *)pdh;
     c->part = (double *)ppart; c->loss = (float *)ploss; c->ksp = (float *)pksp;
+    c->ksp_floats = (long)MLP_SPLITK_MAX * maxio;
   }
   return off;
 }
@@ -179,11 +181,15 @@ static int backward(fdlb_mlp h, const float *t_dev, int M) {
     const int in = h->din[l], out = h->dout[l];
     // dW = dZ^T H_l : A(o, m) = dZ[m][o], B(m, i) = H_l[m][i]
     MCHK(mlp_gemm_splitk(h->dZb, h->H[l], h->g + h->woff[l], out, in, M, 1, out, in, 1, in, 0, h->ksp, h->s));
-    MCHK(mlp_colsum(h->dZf, h->g + h->boff[l], M, out, h->ksp, h->s));
+    // the output layer's bias gradient from the FP32 dY of the loss; the hidden
+    // layers' ones come with their dZ below
+    if (l == h->L - 1) MCHK(mlp_colsum(h->dZf, h->g + h->boff[l], M, out, h->ksp, h->s));
     if (l > 0) {
       // dH = dZ W_l : A = dZ [M x out], B(o, i) = W_l[o][i]
       MCHK(mlp_gemm(h->dZb, h->wb + h->wboff[l], h->dH, M, in, out, out, 1, in, 1, in, 0, h->s));
-      MCHK(mlp_gelu_bwd(h->dH, h->Z[l - 1], h->dZb, h->dZf, (long)M * in, h->s));
+      // dZ_{l-1} = dH * GELU'(Z_{l-1}) and the bias gradient of layer l - 1
+      MCHK(mlp_gelu_bwd_colsum(h->dH, h->Z[l - 1], h->dZb, h->g + h->boff[l - 1], M, in, h->ksp,
+                               (int)std::min<long>(64, h->ksp_floats / in), h->s));
     }
   }
   return FDLB_OK;

@@ -287,13 +287,37 @@ __global__ void k_bias_act(float *__restrict__ Z, const float *__restrict__ b, u
   }
 }
 
-// dZ = dH * GELU'(Z) in BF16 (and fp32 copy for the bias gradient)
-__global__ void k_gelu_bwd(const float *__restrict__ dH, const float *__restrict__ Z, uint16_t *__restrict__ dZb,
-                           float *__restrict__ dZf, long n) {
-  for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const float d = dH[i] * gelu_d(Z[i]);
-    dZf[i] = d;
-    dZb[i] = f2bf(d);
+// dZ = dH * GELU'(Z) in BF16, fused with the partial column sums of dZ (FP32)
+// that the bias gradient needs: block (x, y) takes columns 64 x .. 64 x + 63
+// of rows y R .. y R + R - 1 (R = ceil(M / gridDim.y)) with 16 waves; wave w
+// takes rows w, w + 16, ... of the slice, and the 16 wave sums are added in
+// wave order into part[y][n] (a fixed order).  k_splitk_sum then adds the
+// slices in order.
+constexpr int GB_WAVES = 16;
+__global__ void __launch_bounds__(64 * GB_WAVES) k_gelu_bwd_colsum(const float *__restrict__ dH,
+                                                                   const float *__restrict__ Z,
+                                                                   uint16_t *__restrict__ dZb,
+                                                                   float *__restrict__ part, int M, int N) {
+  __shared__ float red[GB_WAVES][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int n = blockIdx.x * 64 + lane;
+  const int R = (M + gridDim.y - 1) / gridDim.y, r0 = blockIdx.y * R, r1 = min(M, r0 + R);
+  float sum = 0.f;
+  if (n < N) {
+#pragma unroll 4
+    for (int m = r0 + wv; m < r1; m += GB_WAVES) {
+      const long i = (long)m * N + n;
+      const float d = dH[i] * gelu_d(Z[i]);
+      dZb[i] = f2bf(d);
+      sum += d;
+    }
+  }
+  red[wv][lane] = sum;
+  __syncthreads();
+  if (wv == 0 && n < N) {
+    float t = 0.f;
+    for (int w = 0; w < GB_WAVES; w++) t += red[w][lane];
+    part[(long)blockIdx.y * N + n] = t;
   }
 }
 
@@ -349,6 +373,7 @@ __global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ d
   float s0 = 0.f, s1 = 0.f;
   if (n < N) {
     int m = r0 + wv;
+#pragma unroll 4
     for (; m + 4 < r1; m += 8) {
       s0 += dZ[(long)m * N + n];
       s1 += dZ[(long)(m + 4) * N + n];
@@ -360,13 +385,21 @@ __global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ d
   if (wv == 0 && n < N) part[(long)blockIdx.y * N + n] = ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
 }
 
-// C[m][n] (ldc) (+)= sum over z of P[z][m][n] (slices of M x N), in z order
+// C[m][n] (ldc) (+)= sum over z of P[z][m][n] (slices of M x N), in z order;
+// the loads of eight slices are issued before their adds
 __global__ void k_splitk_sum(const float *__restrict__ P, float *__restrict__ C, int M, int N, int S, int ldc,
                              int accumulate) {
   const long mn = (long)M * N;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < mn; i += (long)gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int z = 0; z < S; z++) s += P[z * mn + i];
+    for (int z0 = 0; z0 < S; z0 += 8) {
+      float v[8];
+#pragma unroll
+      for (int j = 0; j < 8; j++) v[j] = z0 + j < S ? P[(z0 + j) * mn + i] : 0.f;
+#pragma unroll
+      for (int j = 0; j < 8; j++)
+        if (z0 + j < S) s += v[j];
+    }
     const long o = (i / N) * ldc + i % N;
     C[o] = accumulate ? C[o] + s : s;
   }
@@ -444,14 +477,22 @@ hipError_t mlp_bias_act(float *Z, const float *b, uint16_t *H, int M, int N, int
   return hipGetLastError();
 }
 
-hipError_t mlp_gelu_bwd(const float *dH, const float *Z, uint16_t *dZb, float *dZf, long n, hipStream_t s) {
-  hipLaunchKernelGGL(k_gelu_bwd, dim3(blocks_for(n)), dim3(256), 0, s, dH, Z, dZb, dZf, n);
+hipError_t mlp_gelu_bwd_colsum(const float *dH, const float *Z, uint16_t *dZb, float *db, int M, int N, float *partial,
+                               int max_slices, hipStream_t s) {
+  // row slices of at least 16 rows (one per wave), at most 64 of them and at
+  // most max_slices (partial holds slices x N floats)
+  int S = M / 16;
+  if (S > 64) S = 64;
+  if (S > max_slices) S = max_slices;
+  if (S < 1) S = 1;
+  hipLaunchKernelGGL(k_gelu_bwd_colsum, dim3((N + 63) / 64, S), dim3(64 * GB_WAVES), 0, s, dH, Z, dZb, partial, M, N);
+  hipLaunchKernelGGL(k_splitk_sum, dim3(blocks_for(N)), dim3(256), 0, s, partial, db, 1, N, S, N, 0);
   return hipGetLastError();
 }
 
 hipError_t mlp_mse(const float *Y, const float *T, uint16_t *dYb, float *dYf, double *part, long n, float *loss,
                    hipStream_t s) {
-  const int nb = 256;
+  const int nb = MLP_LOSS_PARTS;
   hipLaunchKernelGGL(k_mse, dim3(nb), dim3(256), 0, s, Y, T, dYb, dYf, part, n);
   hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(64), 0, s, part, nb, n, loss);
   return hipGetLastError();
