@@ -448,7 +448,7 @@ static int blocks_for(long n);
 int mlp_splitk_slices(int M, int N, int K) {
   const int tiles = ((N + GT - 1) / GT) * ((M + GT - 1) / GT);
   if (tiles >= 64 || K < 512) return 1;
-  int S = 128 / tiles;
+  int S = 512 / tiles;
   if (S > K / 256) S = K / 256;
   if (S > MLP_SPLITK_MAX) S = MLP_SPLITK_MAX;
   return S < 1 ? 1 : S;
