@@ -33,6 +33,8 @@ struct fdlb_mlp_ctx {
   hipStream_t s;
   float *p, *m, *v, *g;
   long *wmap;
+  long *wmapT;                          // parameter -> BF16 transposed copy (weights only, else -1)
+  uint16_t *wbT;                        // BF16 weights transposed: W_l^T [in][out] per layer
   uint16_t *wb;
   std::vector<uint16_t *> H;            // bf16 layer inputs
   std::vector<float *> Z;               // fp32 pre-activations
@@ -68,7 +70,7 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
   size_t off = 0;
   auto take = [&](size_t bytes) { size_t o = off; off += al(bytes); return base ? base + o : nullptr; };
   char *pp = take(4 * P), *pm = take(4 * P), *pv = take(4 * P), *pg = take(4 * P);
-  char *pwm = take(8 * P), *pwb = take(2 * PW);
+  char *pwm = take(8 * P), *pwb = take(2 * PW), *pwmt = take(8 * P), *pwbt = take(2 * PW);
   std::vector<char *> ph(L + 1), pz(L);
   for (int l = 0; l < L; l++) ph[l] = take(2 * (size_t)maxb * din[l]);
   ph[L] = nullptr;
@@ -83,6 +85,7 @@ static size_t layout(int nin, int w, int depth, int nout, int maxb, fdlb_mlp_ctx
     c->din = din; c->dout = dout; c->woff = woff; c->boff = boff; c->wboff = wboff; c->P = P; c->PW = PW;
     c->p = (float *)pp; c->m = (float *)pm; c->v = (float *)pv; c->g = (float *)pg;
     c->wmap = (long *)pwm; c->wb = (uint16_t *)pwb;
+    c->wmapT = (long *)pwmt; c->wbT = (uint16_t *)pwbt;
     c->H.resize(L); c->Z.resize(L);
     for (int l = 0; l < L; l++) { c->H[l] = (uint16_t *)ph[l]; c->Z[l] = (float *)pz[l]; }
     c->dZb = (uint16_t *)pdzb; c->dZf = (float *)pdzf; c->dH = (float *)pdh;
@@ -108,14 +111,20 @@ extern "C" int fdlb_mlp_init(int nin, int width, int depth, int nout, int max_ba
   layout(nin, width, depth, nout, max_batch, c, (char *)ws);
   c->s = (hipStream_t)stream;
   c->t = 0;
-  std::vector<long> wm(c->P, -1);
+  std::vector<long> wm(c->P, -1), wmt(c->P, -1);
   for (int l = 0; l < c->L; l++)
-    for (long i = 0; i < (long)c->din[l] * c->dout[l]; i++) wm[c->woff[l] + i] = c->wboff[l] + i;
+    for (long i = 0; i < (long)c->din[l] * c->dout[l]; i++) {
+      const long o = i / c->din[l], k = i % c->din[l];   // W_l[o][k]
+      wm[c->woff[l] + i] = c->wboff[l] + i;
+      wmt[c->woff[l] + i] = c->wboff[l] + k * c->dout[l] + o;
+    }
   hipError_t e = hipMemcpyAsync(c->wmap, wm.data(), 8 * c->P, hipMemcpyHostToDevice, c->s);
+  if (e == hipSuccess) e = hipMemcpyAsync(c->wmapT, wmt.data(), 8 * c->P, hipMemcpyHostToDevice, c->s);
   if (e == hipSuccess) e = hipMemsetAsync(c->m, 0, 4 * c->P, c->s);
   if (e == hipSuccess) e = hipMemsetAsync(c->v, 0, 4 * c->P, c->s);
   if (e == hipSuccess) e = hipMemsetAsync(c->p, 0, 4 * c->P, c->s);
   if (e == hipSuccess) e = hipMemsetAsync(c->wb, 0, 2 * c->PW, c->s);
+  if (e == hipSuccess) e = hipMemsetAsync(c->wbT, 0, 2 * c->PW, c->s);
   if (e == hipSuccess) e = hipStreamSynchronize(c->s);
   if (e != hipSuccess) { delete c; return mfail(FDLB_EHIP, hipGetErrorString(e)); }
   *out = c;
@@ -139,7 +148,8 @@ extern "C" int fdlb_mlp_set_params(fdlb_mlp h, const float *host) {
   MCHK(hipMemsetAsync(h->v, 0, 4 * h->P, h->s));
   MCHK(hipMemsetAsync(h->g, 0, 4 * h->P, h->s));
   // lr = 0, wd = 0 AdamW pass refreshes the BF16 copies from the masters
-  MCHK(mlp_adamw(h->p, h->m, h->v, h->g, h->P, 0.f, 0.9f, 0.999f, 1e-8f, 0.f, 1.f, 1.f, h->wmap, h->wb, h->s));
+  MCHK(mlp_adamw(h->p, h->m, h->v, h->g, h->P, 0.f, 0.9f, 0.999f, 1e-8f, 0.f, 1.f, 1.f, h->wmap, h->wb, h->wmapT,
+                 h->wbT, h->s));
   MCHK(hipMemsetAsync(h->m, 0, 4 * h->P, h->s));
   MCHK(hipMemsetAsync(h->v, 0, 4 * h->P, h->s));
   MCHK(hipStreamSynchronize(h->s));
@@ -185,8 +195,9 @@ static int backward(fdlb_mlp h, const float *t_dev, int M) {
     // layers' ones come with their dZ below
     if (l == h->L - 1) MCHK(mlp_colsum(h->dZf, h->g + h->boff[l], M, out, h->ksp, h->s));
     if (l > 0) {
-      // dH = dZ W_l : A = dZ [M x out], B(o, i) = W_l[o][i]
-      MCHK(mlp_gemm(h->dZb, h->wb + h->wboff[l], h->dH, M, in, out, out, 1, in, 1, in, 0, h->s));
+      // dH = dZ W_l : A = dZ [M x out], B(o, i) = W_l[o][i] = W_l^T[i][o], read from
+      // the transposed copy so that both operands are contiguous along the depth
+      MCHK(mlp_gemm(h->dZb, h->wbT + h->wboff[l], h->dH, M, in, out, out, 1, 1, out, in, 0, h->s));
       // dZ_{l-1} = dH * GELU'(Z_{l-1}) and the bias gradient of layer l - 1
       MCHK(mlp_gelu_bwd_colsum(h->dH, h->Z[l - 1], h->dZb, h->g + h->boff[l - 1], M, in, h->ksp,
                                (int)std::min<long>(64, h->ksp_floats / in), h->s));
@@ -216,7 +227,8 @@ extern "C" int fdlb_mlp_train_step(fdlb_mlp h, const float *x_dev, const float *
   h->t += 1;
   const float b1 = 0.9f, b2 = 0.999f;
   const float c1 = 1.f - powf(b1, (float)h->t), c2 = 1.f - powf(b2, (float)h->t);
-  MCHK(mlp_adamw(h->p, h->m, h->v, h->g, h->P, lr, b1, b2, 1e-8f, weight_decay, c1, c2, h->wmap, h->wb, h->s));
+  MCHK(mlp_adamw(h->p, h->m, h->v, h->g, h->P, lr, b1, b2, 1e-8f, weight_decay, c1, c2, h->wmap, h->wb, h->wmapT,
+                 h->wbT, h->s));
   if (loss_host) {
     MCHK(hipMemcpyAsync(loss_host, h->loss, 4, hipMemcpyDeviceToHost, h->s));
     MCHK(hipStreamSynchronize(h->s));

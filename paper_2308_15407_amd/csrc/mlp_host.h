@@ -27,5 +27,6 @@ hipError_t mlp_mse(const float *Y, const float *T, uint16_t *dYb, float *dYf, do
 hipError_t mlp_colsum(const float *dZ, float *db, int M, int N, float *partial, hipStream_t s);
 hipError_t mlp_to_bf16(const float *x, uint16_t *y, long n, hipStream_t s);
 hipError_t mlp_adamw(float *p, float *m, float *v, const float *g, long n, float lr, float b1, float b2, float eps,
-                     float wd, float c1, float c2, const long *wmap, uint16_t *wb, hipStream_t s);
+                     float wd, float c1, float c2, const long *wmap, uint16_t *wb, const long *wmapT,
+                     uint16_t *wbT, hipStream_t s);
 }  // namespace fdlb

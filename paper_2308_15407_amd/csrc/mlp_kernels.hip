@@ -412,7 +412,8 @@ __global__ void k_to_bf16(const float *__restrict__ x, uint16_t *__restrict__ y,
 // AdamW on the fp32 master parameters; refresh the BF16 weight copies
 __global__ void k_adamw(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
                         const float *__restrict__ g, long n, float lr, float b1, float b2, float eps, float wd,
-                        float c1, float c2, const long *__restrict__ wmap, uint16_t *__restrict__ wb) {
+                        float c1, float c2, const long *__restrict__ wmap, uint16_t *__restrict__ wb,
+                        const long *__restrict__ wmapT, uint16_t *__restrict__ wbT) {
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
     const float gi = g[i];
     const float mi = b1 * m[i] + (1.0f - b1) * gi;
@@ -423,7 +424,11 @@ __global__ void k_adamw(float *__restrict__ p, float *__restrict__ m, float *__r
     pi -= lr * (mi / c1 / (sqrtf(vi / c2) + eps) + wd * pi);
     p[i] = pi;
     const long w = wmap[i];
-    if (w >= 0) wb[w] = f2bf(pi);
+    if (w >= 0) {
+      const uint16_t b = f2bf(pi);
+      wb[w] = b;
+      wbT[wmapT[i]] = b;
+    }
   }
 }
 
@@ -514,8 +519,10 @@ hipError_t mlp_to_bf16(const float *x, uint16_t *y, long n, hipStream_t s) {
 }
 
 hipError_t mlp_adamw(float *p, float *m, float *v, const float *g, long n, float lr, float b1, float b2, float eps,
-                     float wd, float c1, float c2, const long *wmap, uint16_t *wb, hipStream_t s) {
-  hipLaunchKernelGGL(k_adamw, dim3(blocks_for(n)), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, wd, c1, c2, wmap, wb);
+                     float wd, float c1, float c2, const long *wmap, uint16_t *wb, const long *wmapT,
+                     uint16_t *wbT, hipStream_t s) {
+  hipLaunchKernelGGL(k_adamw, dim3(blocks_for(n)), dim3(256), 0, s, p, m, v, g, n, lr, b1, b2, eps, wd, c1, c2, wmap, wb,
+                     wmapT, wbT);
   return hipGetLastError();
 }
 
