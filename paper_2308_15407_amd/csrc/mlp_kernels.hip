@@ -386,18 +386,18 @@ __global__ void __launch_bounds__(256) k_colsum_part(const float *__restrict__ d
 }
 
 // C[m][n] (ldc) (+)= sum over z of P[z][m][n] (slices of M x N), in z order;
-// the loads of eight slices are issued before their adds
+// the loads of sixteen slices are issued before their adds
 __global__ void k_splitk_sum(const float *__restrict__ P, float *__restrict__ C, int M, int N, int S, int ldc,
                              int accumulate) {
   const long mn = (long)M * N;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < mn; i += (long)gridDim.x * blockDim.x) {
     float s = 0.f;
-    for (int z0 = 0; z0 < S; z0 += 8) {
-      float v[8];
+    for (int z0 = 0; z0 < S; z0 += 16) {
+      float v[16];
 #pragma unroll
-      for (int j = 0; j < 8; j++) v[j] = z0 + j < S ? P[(z0 + j) * mn + i] : 0.f;
+      for (int j = 0; j < 16; j++) v[j] = z0 + j < S ? P[(z0 + j) * mn + i] : 0.f;
 #pragma unroll
-      for (int j = 0; j < 8; j++)
+      for (int j = 0; j < 16; j++)
         if (z0 + j < S) s += v[j];
     }
     const long o = (i / N) * ldc + i % N;
