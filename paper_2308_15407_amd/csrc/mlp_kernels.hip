@@ -280,8 +280,12 @@ __device__ __forceinline__ float gelu_d(float z) {
 __global__ void k_bias_act(float *__restrict__ Z, const float *__restrict__ b, uint16_t *__restrict__ H, int M,
                            int N, int act) {
   const long n = (long)M * N;
+  // the column by 32-bit arithmetic where the index fits (a 64-bit remainder
+  // is a long instruction sequence)
+  const bool i32 = n <= 0x7fffffffL;
   for (long i = blockIdx.x * (long)blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-    const float z = Z[i] + b[i % N];
+    const int col = i32 ? (int)((unsigned)i % (unsigned)N) : (int)(i % N);
+    const float z = Z[i] + b[col];
     Z[i] = z;
     if (act) H[i] = f2bf(gelu(z));
   }
@@ -400,7 +404,7 @@ __global__ void k_splitk_sum(const float *__restrict__ P, float *__restrict__ C,
       for (int j = 0; j < 16; j++)
         if (z0 + j < S) s += v[j];
     }
-    const long o = (i / N) * ldc + i % N;
+    const long o = ldc == N ? i : (i / N) * ldc + i % N;
     C[o] = accumulate ? C[o] + s : s;
   }
 }
